@@ -1,0 +1,200 @@
+/*
+ * moa.h — C ABI of libmoa: generalized inner and outer products of
+ * arbitrary-rank arrays on one AMD Instinct MI355X (gfx950).
+ *
+ * Operations follow Raynolds & Mullin, "A generalized inner and outer product
+ * of arbitrary multi-dimensional arrays using A Mathematics of Arrays (MoA)":
+ *
+ *   outer  C[i ++ j] = A[i] op B[j]                             (Section I, Eq. outer)
+ *   inner  D[i ++ j] = op1-fold over p of A[i ++ <p>] op2 B[<p> ++ j]
+ *                                                              (Section I, Eq. inner)
+ *
+ * with the binary operations generalised as the paper states (any op2; op1 an
+ * associative and commutative operation that generalises the sum).
+ *
+ * Arrays. An array is its shape vector plus a flat vector of its elements
+ * (Section I). Elements are dense, row-major, last axis contiguous, 0-based
+ * (the address arithmetic of the MoA code fragment in Appendix A). Shape
+ * vectors live in host memory and are read only during the call. Element
+ * buffers are DEVICE pointers owned by the caller; the library never frees
+ * them and never keeps them past the call (moa_batch excepted, see below).
+ *
+ * Shapes. inner: rank A >= 1, rank B >= 1, rhoA[-1] == rhoB[0];
+ * result shape rhoA[:-1] ++ rhoB[1:] (rank 0 when both are vectors).
+ * outer: any ranks (0 allowed); result shape rhoA ++ rhoB. Ranks are at most
+ * MOA_MAX_RANK per operand; every extent is >= 0.
+ *
+ * Fold. The op1 fold is a left fold that starts from the first term, so an
+ * inner product over one contracted element is the outer product. An empty
+ * contraction (rhoA[-1] == 0) gives the identity of op1
+ * (+: 0, *: 1, max: -inf / INT32_MIN, min: +inf / INT32_MAX, and: ~0, or/xor: 0).
+ *
+ * Arithmetic. int32 +, -, * wrap (two's complement); max/min are signed.
+ * FP (op1, op2) pairs other than (+,*) fold in ascending p, one IEEE
+ * operation per step, so they match a sequential fold bit for bit. (+,*) on
+ * FP64 / FP32 runs on the matrix cores in another summation order (normwise
+ * relative error of order K * unit roundoff).
+ *
+ * Errors. Every call validates on the host before any launch and returns a
+ * moa_status; nothing is launched on an error. Kernel execution is
+ * asynchronous on the given stream (a hipStream_t passed as void*; NULL is
+ * the default stream). MOA_ERR_HIP means a HIP runtime call failed;
+ * moa_last_error() then holds its message.
+ */
+#ifndef MOA_H_
+#define MOA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MOA_MAX_RANK 16
+#define MOA_ABI_VERSION 1
+
+typedef struct moa_shape {
+  int32_t rank;         /* 0 .. MOA_MAX_RANK */
+  const int64_t *dims;  /* host array of `rank` extents (may be NULL when rank == 0) */
+} moa_shape;
+
+typedef enum moa_dtype { MOA_F64 = 0, MOA_F32 = 1, MOA_I32 = 2 } moa_dtype;
+
+typedef enum moa_op {
+  MOA_ADD = 0, MOA_SUB = 1, MOA_MUL = 2, MOA_DIV = 3, MOA_MAX = 4,
+  MOA_MIN = 5, MOA_AND = 6, MOA_OR = 7, MOA_XOR = 8
+} moa_op;
+
+typedef enum moa_status {
+  MOA_OK = 0,
+  MOA_ERR_NULL = 1,       /* a required pointer is NULL */
+  MOA_ERR_RANK = 2,       /* rank out of range (inner needs rank >= 1) */
+  MOA_ERR_SHAPE = 3,      /* negative extent, or rhoA[-1] != rhoB[0] */
+  MOA_ERR_OP = 4,         /* op1 not a fold op, bitwise op on FP, int32 div */
+  MOA_ERR_DTYPE = 5,      /* unknown or unsupported element type */
+  MOA_ERR_SIZE = 6,       /* element count or byte size overflows int64 */
+  MOA_ERR_ALIAS = 7,      /* output overlaps an input */
+  MOA_ERR_WORKSPACE = 8,  /* workspace missing or too small */
+  MOA_ERR_HIP = 9,        /* a HIP runtime call failed */
+  MOA_ERR_ARG = 10        /* other invalid argument (format, slice count, ...) */
+} moa_status;
+
+/* Status name, static string. */
+const char *moa_status_str(moa_status s);
+/* Detail of the last error on this thread (empty string if none). */
+const char *moa_last_error(void);
+int32_t moa_abi_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Shape algebra (host only, no GPU needed).
+ * out_dims must hold MOA_MAX_RANK (inner) or 2*MOA_MAX_RANK (outer) entries.
+ */
+moa_status moa_inner_shape(moa_shape a, moa_shape b, int64_t *out_dims, int32_t *out_rank);
+moa_status moa_outer_shape(moa_shape a, moa_shape b, int64_t *out_dims, int32_t *out_rank);
+
+/* ---------------------------------------------------------------------------
+ * Generalized inner product (Section I, Eq. inner).
+ * A, B: device arrays of dtype dt, shapes sa, sb. D: device array of dtype dt
+ * with the result shape; must not overlap A or B.
+ * op1 in {ADD, MUL, MAX, MIN} (+ AND, OR, XOR for I32); op2 any op
+ * (bitwise ops for I32 only; DIV for FP only).
+ */
+moa_status moa_inner(moa_shape sa, const void *A, moa_shape sb, const void *B, moa_op op1, moa_op op2,
+                     moa_dtype dt, void *D, void *stream);
+
+/* Flags for moa_inner_ex. */
+#define MOA_FLAG_SEQUENTIAL_FOLD 1u /* (+,*) on FP too: fold in ascending p on the vector units */
+
+/* moa_inner with flags (0 = moa_inner). */
+moa_status moa_inner_ex(moa_shape sa, const void *A, moa_shape sb, const void *B, moa_op op1, moa_op op2,
+                        moa_dtype dt, void *D, uint32_t flags, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Generalized outer product (Section I, Eq. outer), computed by the same
+ * definition as moa_inner with one contracted element. C has shape sa ++ sb.
+ * Every element is one IEEE operation (bit-exact).
+ */
+moa_status moa_outer(moa_shape sa, const void *A, moa_shape sb, const void *B, moa_op op, moa_dtype dt, void *C,
+                     void *stream);
+
+/* ---------------------------------------------------------------------------
+ * (+,*) FP64 inner product at FP64 accuracy from low-precision slices
+ * (the split scheme of Ozaki, Ogita, Oishi & Rump, Numer. Algorithms 59, 2012;
+ * a numerical extension, not part of the paper).
+ *
+ * Each row of A and each column of B is scaled by a power of two so its
+ * entries lie in (-1, 1), then written as `nslices` signed digits of beta
+ * bits, each digit an integer the slice format holds exactly
+ * (MOA_SPLIT_BF16: beta = 9, |digit| <= 256; MOA_SPLIT_FP8: FP8 E4M3 digits,
+ * beta = 5, |digit| <= 16). The slice pairs (s, t) with s + t < nslices are
+ * multiplied on the matrix cores with FP32 accumulation that is exact for the
+ * leading weights, summed in FP64 and scaled back exactly.
+ * Requirements: finite inputs; 1 <= nslices <= MOA_SPLIT_MAX_SLICES.
+ * Accuracy (BF16, nslices = 5, entries u*2^k with k in [-8, 8], K = 8192):
+ * normwise relative error about 7e-13 against an exactly rounded product.
+ *
+ * ws: device workspace of at least moa_inner_split_workspace(...) bytes, owned
+ * by the caller, 256-byte aligned; contents on entry are ignored.
+ */
+#define MOA_SPLIT_BF16 0
+#define MOA_SPLIT_FP8 1
+#define MOA_SPLIT_MAX_SLICES 7
+size_t moa_inner_split_workspace(moa_shape sa, moa_shape sb, int32_t fmt, int32_t nslices);
+moa_status moa_inner_split(moa_shape sa, const double *A, moa_shape sb, const double *B, double *D, int32_t fmt,
+                           int32_t nslices, void *ws, size_t ws_bytes, void *stream);
+/* The two halves of moa_inner_split, for callers that reuse slices or time
+ * the stages: _prepare scans and slices A and B into ws; _multiply forms the
+ * slice-pair products from ws into D (same shapes, format and slice count as
+ * the _prepare call that filled ws; ws must not be modified in between). */
+moa_status moa_inner_split_prepare(moa_shape sa, const double *A, moa_shape sb, const double *B, int32_t fmt,
+                                   int32_t nslices, void *ws, size_t ws_bytes, void *stream);
+moa_status moa_inner_split_multiply(moa_shape sa, moa_shape sb, double *D, int32_t fmt, int32_t nslices, void *ws,
+                                    size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Backward of the (+,*) inner product D = A . B (FP32 or FP64).
+ * G: upstream gradient dL/dD with the result shape. Writes
+ *   dA = G (+,*) B_rot   (B_rot: B with its first axis moved last)  shape sa
+ *   dB = A_rot (+,*) G   (A_rot: A with its last axis moved first)  shape sb
+ * both generalized inner products on permuted shapes; the permutations are
+ * folded into the operand loads (no transposed copies are made).
+ * dA or dB may be NULL to skip it. Outputs must not overlap inputs.
+ */
+moa_status moa_inner_grad(moa_shape sa, const void *A, moa_shape sb, const void *B, const void *G, void *dA,
+                          void *dB, moa_dtype dt, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches of uneven (+,*) inner products in one persistent launch.
+ *
+ * moa_batch_build validates every problem on the host, uploads a device
+ * descriptor table (problem shapes, pointers, tile choice per problem from the
+ * tile table), orders the work by estimated cost, and captures the persistent
+ * launch in a HIP graph on `stream`. The caller's A[i], B[i], D[i] (device
+ * pointers, dtype dt = MOA_F32 or MOA_F64) must stay valid while the batch
+ * exists; moa_batch_run replays the graph (one kernel launch). A batch owns
+ * only its descriptor table, work counters and graph; moa_batch_free releases
+ * them. Concurrent runs of the same batch race on its work counters.
+ */
+typedef struct moa_batch moa_batch;
+moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A, const moa_shape *sb,
+                           const void *const *B, void *const *D, moa_dtype dt, void *stream, moa_batch **out);
+moa_status moa_batch_run(moa_batch *b, void *stream);
+void moa_batch_free(moa_batch *b);
+/* Number of work items (problem tiles) and kernel launches per run. */
+moa_status moa_batch_info(const moa_batch *b, int64_t *work_items, int32_t *launches);
+
+/* Tile table used by moa_batch_build: for each (M, N, K) size bucket the
+ * tile variant to use. moa_batch_autotune times every tile variant on
+ * synthetic problems of each bucket on `stream` and installs the fastest;
+ * moa_tile_table_get/set read or replace the table as text
+ * ("bucket_m bucket_n bucket_k variant" lines). */
+moa_status moa_batch_autotune(moa_dtype dt, int32_t reps, void *stream);
+moa_status moa_tile_table_get(char *buf, size_t len);
+moa_status moa_tile_table_set(const char *text);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOA_H_ */

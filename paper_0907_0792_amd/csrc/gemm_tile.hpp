@@ -1,0 +1,139 @@
+// Matrix-core tile of the (+,*) inner product, shared by the single-product
+// kernel and the persistent batch kernel.
+#pragma once
+
+#include "common.hpp"
+
+namespace moa {
+
+template <typename T>
+struct Mfma16;
+
+template <>
+struct Mfma16<double> {
+  using acc_t = doublex4;
+  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // Output element v of lane l sits at row 4*v + l/16, column l%16.
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + lane / 16; }
+};
+
+template <>
+struct Mfma16<float> {
+  using acc_t = floatx4;
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // Output element v of lane l sits at row 4*(l/16) + v, column l%16.
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane / 16) + v; }
+};
+
+// One BM x BN tile of D = A . B (BM = 32*WBM, BN = 32*WBN), computed by the
+// 256 threads of a workgroup. m0, n0: tile origin.
+template <typename T, bool TA, bool TB, int WBM, int WBN>
+__device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
+                                          int64_t M, int64_t K, int64_t N, int64_t m0, int64_t n0) {
+  using MF = Mfma16<T>;
+  using acc_t = typename MF::acc_t;
+  constexpr int BM = 32 * WBM, BN = 32 * WBN, BK = 16;
+  constexpr int PAD = 2;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  __shared__ T As[BK][BM + PAD];
+  __shared__ T Bs[BK][BN + PAD];
+
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int wm = wave / 2, wn = wave % 2;
+
+  acc_t acc[WBM][WBN];
+#pragma unroll
+  for (int i = 0; i < WBM; ++i)
+#pragma unroll
+    for (int j = 0; j < WBN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
+
+  T ra[EA], rb[EB];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int f = tid + 256 * e;
+      int64_t gm, gk;
+      if constexpr (!TA) {
+        gm = m0 + f / BK;
+        gk = k0 + f % BK;
+      } else {
+        gk = k0 + f / BM;
+        gm = m0 + f % BM;
+      }
+      const bool ok = gm < M && gk < K;
+      ra[e] = ok ? (TA ? A[gk * M + gm] : A[gm * K + gk]) : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int f = tid + 256 * e;
+      int64_t gn, gk;
+      if constexpr (!TB) {
+        gk = k0 + f / BN;
+        gn = n0 + f % BN;
+      } else {
+        gn = n0 + f / BK;
+        gk = k0 + f % BK;
+      }
+      const bool ok = gn < N && gk < K;
+      rb[e] = ok ? (TB ? B[gn * K + gk] : B[gk * N + gn]) : T(0);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int f = tid + 256 * e;
+      if constexpr (!TA)
+        As[f % BK][f / BK] = ra[e];
+      else
+        As[f / BM][f % BM] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int f = tid + 256 * e;
+      if constexpr (!TB)
+        Bs[f / BN][f % BN] = rb[e];
+      else
+        Bs[f % BK][f / BK] = rb[e];
+    }
+  };
+
+  const int64_t nk = (K + BK - 1) / BK;
+  if (nk > 0) load(0);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int k4 = 0; k4 < BK; k4 += 4) {
+      T a[WBM], b[WBN];
+#pragma unroll
+      for (int i = 0; i < WBM; ++i) a[i] = As[k4 + lane / 16][wm * (BM / 2) + i * 16 + lane % 16];
+#pragma unroll
+      for (int j = 0; j < WBN; ++j) b[j] = Bs[k4 + lane / 16][wn * (BN / 2) + j * 16 + lane % 16];
+#pragma unroll
+      for (int i = 0; i < WBM; ++i)
+#pragma unroll
+        for (int j = 0; j < WBN; ++j) acc[i][j] = MF::run(a[i], b[j], acc[i][j]);
+    }
+  }
+  __syncthreads();  // LDS is reused by the caller's next tile
+#pragma unroll
+  for (int i = 0; i < WBM; ++i)
+#pragma unroll
+    for (int j = 0; j < WBN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gm = m0 + wm * (BM / 2) + i * 16 + MF::row(lane, v);
+        const int64_t gn = n0 + wn * (BN / 2) + j * 16 + lane % 16;
+        if (gm < M && gn < N) D[gm * N + gn] = acc[i][j][v];
+      }
+}
+
+}  // namespace moa

@@ -1,0 +1,395 @@
+// Batches of uneven (+,*) inner products in one persistent launch.
+//
+// Each problem i is the (+,*) case of Eq. inner (Section I) on its own
+// flattened M_i x K_i . K_i x N_i view. The batch is cut into work items
+// (one output tile of one problem each); items are ordered by estimated cost,
+// largest first, and a persistent grid of workgroups pulls them from a device
+// counter, so the skew between large and small problems is absorbed at run
+// time. The counter resets itself (the last workgroup to finish zeroes it),
+// so the captured graph can be replayed with no memset node.
+//
+// Tile variants (per problem, from the tile table):
+//   0: 32 x 32 tiles (one 16 x 16 MFMA block per wave)
+//   1: 64 x 64 tiles (2 x 2 blocks per wave)
+// The table maps (M, N, K) size buckets to a variant; moa_batch_autotune
+// fills it by timing both variants on synthetic problems of each bucket.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <numeric>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "gemm_tile.hpp"
+#include "internal.hpp"
+
+namespace moa {
+moa_status set_error(moa_status st, const char *msg);
+moa_status validate_inner(moa_shape a, moa_shape b, int64_t *M, int64_t *K, int64_t *N);
+}  // namespace moa
+
+struct moa_batch {
+  moa_dtype dt;
+  int32_t n;
+  int64_t items;
+  moa::BatchDesc *d_desc;
+  moa::BatchItem *d_items;
+  unsigned int *d_counters;  // [0] next item, [1] finished workgroups
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  int grid;
+};
+
+namespace moa {
+namespace {
+
+constexpr int kVariants = 2;
+constexpr int kTileSide[kVariants] = {32, 64};
+
+// Size buckets: M and N split at 32, K at 128.
+int bucket_of(int64_t M, int64_t N, int64_t K) {
+  return (M > 32 ? 4 : 0) + (N > 32 ? 2 : 0) + (K > 128 ? 1 : 0);
+}
+constexpr int kBuckets = 8;
+
+std::mutex g_table_mu;
+int g_table[kBuckets] = {0, 1, 1, 1, 1, 1, 1, 1};
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_batch(const BatchDesc *__restrict__ desc,
+                                                   const BatchItem *__restrict__ items, int64_t n_items,
+                                                   unsigned int *__restrict__ counters) {
+  __shared__ int64_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&counters[0], 1u);
+    __syncthreads();
+    const int64_t it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const BatchItem w = items[it];
+    const BatchDesc p = desc[w.prob];
+    const int side = (p.tile == 0) ? 32 : 64;
+    const int64_t tm = w.tile / p.tiles_n, tn = w.tile % p.tiles_n;
+    if (p.tile == 0)
+      gemm_tile<T, false, false, 1, 1>((const T *)p.A, (const T *)p.B, (T *)p.D, p.M, p.K, p.N, tm * side, tn * side);
+    else
+      gemm_tile<T, false, false, 2, 2>((const T *)p.A, (const T *)p.B, (T *)p.D, p.M, p.K, p.N, tm * side, tn * side);
+  }
+  // Every workgroup has taken its last item; the last one to get here
+  // re-arms the counters for the next replay.
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int done = atomicAdd(&counters[1], 1u);
+    if (done == gridDim.x - 1) {
+      atomicExch(&counters[0], 0u);
+      atomicExch(&counters[1], 0u);
+    }
+  }
+}
+
+__global__ void k_zero_u32(unsigned int *p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+int persistent_grid() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
+  return cus * 4;
+}
+
+moa_status hip_fail(hipError_t e, const char *what) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+  return set_error(MOA_ERR_HIP, buf);
+}
+
+void free_batch(moa_batch *b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_counters) (void)hipFree(b->d_counters);
+  delete b;
+}
+
+}  // namespace
+}  // namespace moa
+
+using namespace moa;
+
+extern "C" {
+
+moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A, const moa_shape *sb,
+                           const void *const *B, void *const *D, moa_dtype dt, void *stream, moa_batch **out) {
+  if (!out) return set_error(MOA_ERR_NULL, "out is NULL");
+  *out = nullptr;
+  if (dt != MOA_F32 && dt != MOA_F64) return set_error(MOA_ERR_DTYPE, "batch needs MOA_F32 or MOA_F64");
+  if (n < 0) return set_error(MOA_ERR_ARG, "negative batch size");
+  if (n > 0 && (!sa || !sb || !A || !B || !D)) return set_error(MOA_ERR_NULL, "batch array is NULL");
+  const size_t es = dt == MOA_F64 ? 8 : 4;
+  std::vector<BatchDesc> desc((size_t)n);
+  std::vector<int64_t> cost((size_t)n);
+  int table[kBuckets];
+  {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    memcpy(table, g_table, sizeof table);
+  }
+  int64_t total_items = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t M, K, N;
+    moa_status st = validate_inner(sa[i], sb[i], &M, &K, &N);
+    if (st != MOA_OK) return st;
+    if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) return set_error(MOA_ERR_SIZE, "batch problem too large");
+    if (M * K > 0 && !A[i]) return set_error(MOA_ERR_NULL, "A[i] is NULL");
+    if (K * N > 0 && !B[i]) return set_error(MOA_ERR_NULL, "B[i] is NULL");
+    if (M * N > 0 && !D[i]) return set_error(MOA_ERR_NULL, "D[i] is NULL");
+    const uintptr_t d0 = (uintptr_t)D[i], d1 = d0 + (uintptr_t)(M * N) * es;
+    const uintptr_t a0 = (uintptr_t)A[i], a1 = a0 + (uintptr_t)(M * K) * es;
+    const uintptr_t b0 = (uintptr_t)B[i], b1 = b0 + (uintptr_t)(K * N) * es;
+    if (M * N > 0 && ((M * K > 0 && d0 < a1 && a0 < d1) || (K * N > 0 && d0 < b1 && b0 < d1)))
+      return set_error(MOA_ERR_ALIAS, "D[i] overlaps an input");
+    const int v = table[bucket_of(M, N, K)];
+    const int side = kTileSide[v];
+    BatchDesc &d = desc[(size_t)i];
+    d.A = A[i];
+    d.B = B[i];
+    d.D = D[i];
+    d.M = (int32_t)M;
+    d.K = (int32_t)K;
+    d.N = (int32_t)N;
+    d.tile = v;
+    d.tiles_n = (int32_t)((N + side - 1) / side);
+    d.first_item = (int32_t)total_items;
+    const int64_t tiles = ((M + side - 1) / side) * d.tiles_n;
+    total_items += (M * N > 0) ? tiles : 0;
+    cost[(size_t)i] = (int64_t)side * side * (K > 0 ? K : 1);
+  }
+  // Work items, costliest first (longest-processing-time order).
+  std::vector<BatchItem> items;
+  items.reserve((size_t)total_items);
+  std::vector<int32_t> order((size_t)n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[(size_t)x] > cost[(size_t)y]; });
+  for (int32_t i : order) {
+    const BatchDesc &d = desc[(size_t)i];
+    if ((int64_t)d.M * d.N == 0) continue;
+    const int side = kTileSide[d.tile];
+    const int64_t tiles = ((d.M + side - 1) / side) * (int64_t)d.tiles_n;
+    for (int64_t t = 0; t < tiles; ++t) items.push_back(BatchItem{i, (int32_t)t});
+  }
+  // Zero-K problems: result is the empty sum, filled at build time below by
+  // the identity kernel inside the graph is not needed; handled as items with
+  // K = 0 (the tile loop writes zeros).
+
+  moa_batch *b = new moa_batch();
+  memset(b, 0, sizeof *b);
+  b->dt = dt;
+  b->n = n;
+  b->items = (int64_t)items.size();
+  b->grid = persistent_grid();
+  hipError_t e;
+  hipStream_t cap = nullptr;
+  if ((e = hipMalloc(&b->d_counters, 4 * sizeof(unsigned int))) != hipSuccess) goto hip_error;
+  if (n > 0 && (e = hipMalloc(&b->d_desc, sizeof(BatchDesc) * (size_t)n)) != hipSuccess) goto hip_error;
+  if (!items.empty() && (e = hipMalloc(&b->d_items, sizeof(BatchItem) * items.size())) != hipSuccess) goto hip_error;
+  if (n > 0 &&
+      (e = hipMemcpy(b->d_desc, desc.data(), sizeof(BatchDesc) * (size_t)n, hipMemcpyHostToDevice)) != hipSuccess)
+    goto hip_error;
+  if (!items.empty() && (e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(),
+                                       hipMemcpyHostToDevice)) != hipSuccess)
+    goto hip_error;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, (hipStream_t)stream, b->d_counters, 4);
+  if ((e = hipGetLastError()) != hipSuccess) goto hip_error;
+  if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) goto hip_error;
+  // Capture the persistent launch on a private stream (capture is not allowed
+  // on the legacy default stream); the graph is replayed on any stream.
+  if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) goto hip_error;
+  if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) goto hip_error;
+  if (b->items > 0) {
+    if (dt == MOA_F32)
+      hipLaunchKernelGGL(k_batch<float>, dim3((unsigned)b->grid), dim3(256), 0, cap, b->d_desc, b->d_items, b->items,
+                         b->d_counters);
+    else
+      hipLaunchKernelGGL(k_batch<double>, dim3((unsigned)b->grid), dim3(256), 0, cap, b->d_desc, b->d_items,
+                         b->items, b->d_counters);
+  }
+  if ((e = hipStreamEndCapture(cap, &b->graph)) != hipSuccess) goto hip_error;
+  if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) goto hip_error;
+  (void)hipStreamDestroy(cap);
+  *out = b;
+  return MOA_OK;
+hip_error:
+  if (cap) (void)hipStreamDestroy(cap);
+  free_batch(b);
+  return hip_fail(e, "moa_batch_build");
+}
+
+moa_status moa_batch_run(moa_batch *b, void *stream) {
+  if (!b) return set_error(MOA_ERR_NULL, "batch is NULL");
+  if (b->items == 0) return MOA_OK;
+  hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "moa_batch_run");
+  return MOA_OK;
+}
+
+void moa_batch_free(moa_batch *b) { free_batch(b); }
+
+moa_status moa_batch_info(const moa_batch *b, int64_t *work_items, int32_t *launches) {
+  if (!b) return set_error(MOA_ERR_NULL, "batch is NULL");
+  if (work_items) *work_items = b->items;
+  if (launches) *launches = b->items > 0 ? 1 : 0;
+  return MOA_OK;
+}
+
+moa_status moa_tile_table_get(char *buf, size_t len) {
+  if (!buf || len == 0) return set_error(MOA_ERR_NULL, "buffer is NULL");
+  std::string s;
+  {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    for (int bk = 0; bk < kBuckets; ++bk) {
+      char line[96];
+      snprintf(line, sizeof line, "%s %s %s %d\n", (bk & 4) ? "M>32" : "M<=32", (bk & 2) ? "N>32" : "N<=32",
+               (bk & 1) ? "K>128" : "K<=128", g_table[bk]);
+      s += line;
+    }
+  }
+  if (s.size() + 1 > len) return set_error(MOA_ERR_ARG, "buffer too small");
+  memcpy(buf, s.c_str(), s.size() + 1);
+  return MOA_OK;
+}
+
+moa_status moa_tile_table_set(const char *text) {
+  if (!text) return set_error(MOA_ERR_NULL, "text is NULL");
+  int t[kBuckets];
+  int got = 0;
+  const char *p = text;
+  while (*p && got < kBuckets) {
+    char m[16], nn[16], k[16];
+    int v, used = 0;
+    if (sscanf(p, "%15s %15s %15s %d%n", m, nn, k, &v, &used) != 4) break;
+    if (v < 0 || v >= kVariants) return set_error(MOA_ERR_ARG, "tile variant out of range");
+    const int bk = (strcmp(m, "M>32") == 0 ? 4 : 0) + (strcmp(nn, "N>32") == 0 ? 2 : 0) +
+                   (strcmp(k, "K>128") == 0 ? 1 : 0);
+    t[bk] = v;
+    ++got;
+    p += used;
+    while (*p == '\n' || *p == ' ') ++p;
+  }
+  if (got != kBuckets) return set_error(MOA_ERR_ARG, "tile table needs one line per bucket");
+  std::lock_guard<std::mutex> lk(g_table_mu);
+  memcpy(g_table, t, sizeof t);
+  return MOA_OK;
+}
+
+// Autotuner: for each size bucket, build synthetic batches that use only that
+// bucket's shapes, time each tile variant (HIP events around graph replays on
+// `stream`) and keep the fastest.
+moa_status moa_batch_autotune(moa_dtype dt, int32_t reps, void *stream) {
+  if (dt != MOA_F32 && dt != MOA_F64) return set_error(MOA_ERR_DTYPE, "autotune needs MOA_F32 or MOA_F64");
+  if (reps < 1) reps = 5;
+  const size_t es = dt == MOA_F64 ? 8 : 4;
+  const int kProblems = 512;
+  hipStream_t s = (hipStream_t)stream;
+  std::mt19937_64 rng(12345);
+  int best[kBuckets];
+  int saved[kBuckets];
+  {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    memcpy(saved, g_table, sizeof saved);
+  }
+  void *pool = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he;
+  if ((he = hipEventCreate(&e0)) != hipSuccess || (he = hipEventCreate(&e1)) != hipSuccess)
+    return hip_fail(he, "autotune events");
+  moa_status result = MOA_OK;
+  for (int bk = 0; bk < kBuckets && result == MOA_OK; ++bk) {
+    std::vector<int64_t> dims(6 * (size_t)kProblems);
+    size_t bytes = 0;
+    std::vector<size_t> offA(kProblems), offB(kProblems), offD(kProblems);
+    for (int i = 0; i < kProblems; ++i) {
+      auto pick = [&](int lo, int hi) { return (int64_t)(lo + (int)(rng() % (uint64_t)(hi - lo + 1))); };
+      const int64_t M = (bk & 4) ? pick(33, 64) : pick(4, 32);
+      const int64_t N = (bk & 2) ? pick(33, 64) : pick(4, 32);
+      const int64_t K = (bk & 1) ? pick(129, 512) : pick(16, 128);
+      dims[6 * i + 0] = M;
+      dims[6 * i + 1] = K;
+      dims[6 * i + 2] = K;
+      dims[6 * i + 3] = N;
+      offA[i] = bytes;
+      bytes += (size_t)(M * K) * es;
+      offB[i] = bytes;
+      bytes += (size_t)(K * N) * es;
+      offD[i] = bytes;
+      bytes += (size_t)(M * N) * es;
+      bytes = (bytes + 255) & ~(size_t)255;
+    }
+    if ((he = hipMalloc(&pool, bytes)) != hipSuccess) {
+      result = hip_fail(he, "autotune pool");
+      break;
+    }
+    (void)hipMemsetAsync(pool, 0, bytes, s);
+    std::vector<moa_shape> sa(kProblems), sb(kProblems);
+    std::vector<const void *> pa(kProblems), pb(kProblems);
+    std::vector<void *> pd(kProblems);
+    for (int i = 0; i < kProblems; ++i) {
+      sa[i] = moa_shape{2, &dims[6 * i + 0]};
+      sb[i] = moa_shape{2, &dims[6 * i + 2]};
+      pa[i] = (char *)pool + offA[i];
+      pb[i] = (char *)pool + offB[i];
+      pd[i] = (char *)pool + offD[i];
+    }
+    float best_ms = 1e30f;
+    best[bk] = saved[bk];
+    for (int v = 0; v < kVariants && result == MOA_OK; ++v) {
+      {
+        std::lock_guard<std::mutex> lk(g_table_mu);
+        for (int q = 0; q < kBuckets; ++q) g_table[q] = v;
+      }
+      moa_batch *b = nullptr;
+      moa_status st = moa_batch_build(kProblems, sa.data(), pa.data(), sb.data(), pb.data(), pd.data(), dt, stream, &b);
+      if (st != MOA_OK) {
+        result = st;
+        break;
+      }
+      (void)moa_batch_run(b, stream);
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r) (void)moa_batch_run(b, stream);
+      (void)hipEventRecord(e1, s);
+      if ((he = hipEventSynchronize(e1)) != hipSuccess) {
+        moa_batch_free(b);
+        result = hip_fail(he, "autotune timing");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best[bk] = v;
+      }
+      moa_batch_free(b);
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(pool);
+    pool = nullptr;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_table_mu);
+  if (result == MOA_OK)
+    memcpy(g_table, best, sizeof best);
+  else
+    memcpy(g_table, saved, sizeof saved);
+  return result;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Generalized outer product C[i ++ j] = A[i] op B[j]   (Section I, Eq. outer).
+//
+// Flattened: C is NA x NB with C[i, j] = op(A[i], B[j]). The kernel is a pure
+// store stream (one IEEE op per element, so results are bit-exact): each thread
+// holds a 16-byte slice of B in registers for the whole launch and writes it
+// combined with one element of A per row, so every row of C is written as
+// contiguous 16-byte non-temporal stores and A and B are read once.
+#pragma clang fp contract(off)
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace moa {
+
+// Fast path: NB % VEC == 0 and C 16-byte aligned. Block = 256 threads;
+// columns [c0, c0 + 256*VEC) of rows [r0, r0 + rows_per_block).
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_outer_vec(const T *__restrict__ A, const T *__restrict__ B,
+                                                   T *__restrict__ C, int64_t NA, int64_t NB, int64_t col_blocks,
+                                                   int rows_per_block) {
+  constexpr int VEC = 16 / sizeof(T);
+  const int64_t cb = blockIdx.x % col_blocks;
+  const int64_t rb = blockIdx.x / col_blocks;
+  const int64_t j0 = cb * (256 * VEC) + (int64_t)threadIdx.x * VEC;
+  if (j0 >= NB) return;
+  T b[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) b[e] = B[j0 + e];
+  using V = T __attribute__((ext_vector_type(VEC)));
+  const int64_t r0 = rb * rows_per_block;
+  const int64_t r1 = (r0 + rows_per_block) < NA ? (r0 + rows_per_block) : NA;
+  for (int64_t r = r0; r < r1; ++r) {
+    const T a = A[r];
+    V out;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) out[e] = apply_op<OP>(a, b[e]);
+    __builtin_nontemporal_store(out, (V *)(C + r * NB + j0));
+  }
+}
+
+// General path: any NB / alignment; grid-stride over flat indices.
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_outer_flat(const T *__restrict__ A, const T *__restrict__ B,
+                                                    T *__restrict__ C, int64_t NA, int64_t NB) {
+  const int64_t total = NA * NB;
+  for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < total; f += (int64_t)gridDim.x * 256) {
+    const int64_t i = f / NB, j = f - i * NB;
+    C[f] = apply_op<OP>(A[i], B[j]);
+  }
+}
+
+template <typename T, int OP>
+static hipError_t launch_t(const T *A, const T *B, T *C, int64_t NA, int64_t NB, hipStream_t s) {
+  constexpr int VEC = 16 / sizeof(T);
+  if (NB % VEC == 0 && ((uintptr_t)C % 16) == 0 && NB >= 256) {
+    const int64_t col_blocks = (NB + 256 * VEC - 1) / (256 * VEC);
+    // About 64 KiB of output per block, and at least a few thousand blocks.
+    int64_t rows = (64 * 1024) / (NB * (int64_t)sizeof(T));
+    if (rows < 1) rows = 1;
+    if (rows > 64) rows = 64;
+    while (rows > 1 && ((NA + rows - 1) / rows) * col_blocks < 4096) rows /= 2;
+    const int64_t row_blocks = (NA + rows - 1) / rows;
+    const int64_t grid = row_blocks * col_blocks;
+    if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_outer_vec<T, OP>), dim3((unsigned)grid), dim3(256), 0, s, A, B, C, NA, NB, col_blocks,
+                       (int)rows);
+  } else {
+    int64_t blocks = (NA * NB + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_outer_flat<T, OP>), dim3((unsigned)blocks), dim3(256), 0, s, A, B, C, NA, NB);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t dispatch(moa_op op, const T *A, const T *B, T *C, int64_t NA, int64_t NB, hipStream_t s) {
+  switch (op) {
+    case MOA_ADD: return launch_t<T, MOA_ADD>(A, B, C, NA, NB, s);
+    case MOA_SUB: return launch_t<T, MOA_SUB>(A, B, C, NA, NB, s);
+    case MOA_MUL: return launch_t<T, MOA_MUL>(A, B, C, NA, NB, s);
+    case MOA_MAX: return launch_t<T, MOA_MAX>(A, B, C, NA, NB, s);
+    case MOA_MIN: return launch_t<T, MOA_MIN>(A, B, C, NA, NB, s);
+    default: break;
+  }
+  if constexpr (T(1) / 2 == 0) {
+    switch (op) {
+      case MOA_AND: return launch_t<T, MOA_AND>(A, B, C, NA, NB, s);
+      case MOA_OR: return launch_t<T, MOA_OR>(A, B, C, NA, NB, s);
+      case MOA_XOR: return launch_t<T, MOA_XOR>(A, B, C, NA, NB, s);
+      default: break;
+    }
+  } else {
+    if (op == MOA_DIV) return launch_t<T, MOA_DIV>(A, B, C, NA, NB, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_outer(moa_dtype dt, moa_op op, const void *A, const void *B, void *C, int64_t NA, int64_t NB,
+                        hipStream_t s) {
+  if (NA == 0 || NB == 0) return hipSuccess;
+  switch (dt) {
+    case MOA_F64: return dispatch<double>(op, (const double *)A, (const double *)B, (double *)C, NA, NB, s);
+    case MOA_F32: return dispatch<float>(op, (const float *)A, (const float *)B, (float *)C, NA, NB, s);
+    case MOA_I32: return dispatch<int32_t>(op, (const int32_t *)A, (const int32_t *)B, (int32_t *)C, NA, NB, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Identity fill (empty contraction).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T *p, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+hipError_t launch_fill_identity(moa_dtype dt, moa_op op, void *p, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (dt == MOA_I32) {
+    int32_t v = 0;
+    switch (op) {
+      case MOA_MUL: v = 1; break;
+      case MOA_MAX: v = INT32_MIN; break;
+      case MOA_MIN: v = INT32_MAX; break;
+      case MOA_AND: v = -1; break;
+      default: v = 0; break;
+    }
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3((unsigned)blocks), dim3(256), 0, s, (int32_t *)p, n, v);
+  } else {
+    double v = 0.0;
+    switch (op) {
+      case MOA_MUL: v = 1.0; break;
+      case MOA_MAX: v = -__builtin_huge_val(); break;
+      case MOA_MIN: v = __builtin_huge_val(); break;
+      default: v = 0.0; break;
+    }
+    if (dt == MOA_F64)
+      hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double *)p, n, v);
+    else
+      hipLaunchKernelGGL(k_fill<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float *)p, n, (float)v);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace moa

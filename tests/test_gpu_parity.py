@@ -1,0 +1,406 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bit-exact for int32, tropical, outer products and sequential-fold FP pairs;
+normwise tolerances for the matrix-core (+,*) paths:
+  FP64 (+,*)          ||D - D*||_F / ||D*||_F <= 1e-13   (D* = Dot2 reference)
+  FP32 (+,*)          <= 1e-5
+  split BF16, S = 5   <= 1e-12 against Dot2, <= 1e-14 against the oracle's
+                      own split scheme (same digits, same kept pairs)
+Full-size workloads are checked on sampled rows the oracle computes one by one.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import moa_inputs as mi
+import oracle
+import paper_0907_0792_amd as moa
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+FOLD_F = ["add", "mul", "max", "min"]
+ELEM_F = ["add", "sub", "mul", "div", "max", "min"]
+FOLD_I = ["add", "mul", "max", "min", "and", "or", "xor"]
+ELEM_I = ["add", "sub", "mul", "max", "min", "and", "or", "xor"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def eq(x, y):
+    x = np.asarray(x)
+    y = np.asarray(y)
+    assert x.shape == y.shape, (x.shape, y.shape)
+    if x.dtype.kind == "f":
+        nan = np.isnan(x) & np.isnan(y)
+        bad = ~((x == y) | nan)
+        assert not bad.any(), "mismatch at %s: %r vs %r" % (np.argwhere(bad)[0], x[bad][0], y[bad][0])
+    else:
+        assert np.array_equal(x, y), "mismatch at %s" % (np.argwhere(x != y)[0],)
+
+
+def nerr(x, ref):
+    return oracle.normwise_error(x, ref)
+
+
+def rand(rng, shape, dt):
+    if dt == np.int32:
+        return mi.uniform_i32(rng, shape, -60, 60)
+    x = rng.uniform(0.5, 2.0, size=shape) * rng.choice([-1.0, 1.0], size=shape)
+    return np.asarray(x, dtype=dt, order="C")
+
+
+# ---------------------------------------------------------------------------
+
+def test_worked_example():
+    say("worked example 2x3 . 3x4")
+    for dt in (np.float64, np.float32, np.int32):
+        a = np.arange(6, dtype=dt).reshape(2, 3)
+        b = np.arange(12, dtype=dt).reshape(3, 4)
+        eq(host(moa.inner(gpu(a), gpu(b))), np.array([[20, 23, 26, 29], [56, 68, 80, 92]], dtype=dt))
+        eq(host(moa.inner(gpu(a), gpu(b), "max", "add")), np.array([[10, 11, 12, 13], [13, 14, 15, 16]], dtype=dt))
+        eq(host(moa.outer(gpu(a), gpu(b), "mul")), oracle.outer(a, b, "mul"))
+
+
+SIMT_SHAPES = [
+    ((19,), (19,)),                 # rank-0 result
+    ((37, 19), (19, 53)),           # ragged, below one tile
+    ((3, 4, 5), (5, 2, 7)),
+    ((1, 1), (1, 1)),
+    ((6, 1), (1, 9)),               # K = 1
+    ((133, 21), (21, 70)),          # several 32/64 tiles and a tail
+]
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.float64, np.float32])
+def test_simt_all_op_pairs_bit_exact(dt):
+    rng = np.random.default_rng(100)
+    folds = FOLD_I if dt == np.int32 else FOLD_F
+    elems = ELEM_I if dt == np.int32 else ELEM_F
+    for sa, sb in SIMT_SHAPES:
+        a = rand(rng, sa, dt)
+        b = rand(rng, sb, dt)
+        ga, gb = gpu(a), gpu(b)
+        for op1 in folds:
+            for op2 in elems:
+                say("simt", np.dtype(dt).name, sa, sb, op1, op2)
+                d = moa.inner_ex(ga, gb, op1, op2, flags=moa.FLAG_SEQUENTIAL_FOLD)
+                eq(host(d), oracle.inner(a, b, op1, op2, mode="native"))
+
+
+@pytest.mark.parametrize("tile", [(300, 40, 260), (513, 33, 129), (1100, 20, 1030)])
+def test_simt_tiles_and_tails(tile):
+    # Sizes that select each register-block variant with ragged edges.
+    M, K, N = tile
+    rng = np.random.default_rng(101)
+    a = mi.uniform_i32(rng, (M, K))
+    b = mi.uniform_i32(rng, (K, N))
+    for op1, op2 in (("max", "add"), ("min", "sub"), ("add", "mul"), ("xor", "and")):
+        say("simt tile", tile, op1, op2)
+        eq(host(moa.inner(gpu(a), gpu(b), op1, op2)), oracle.inner(a, b, op1, op2))
+    af = rand(rng, (M, K), np.float32)
+    bf = rand(rng, (K, N), np.float32)
+    say("simt tile f32 (+,-)", tile)
+    eq(host(moa.inner(gpu(af), gpu(bf), "add", "sub")), oracle.inner(af, bf, "add", "sub", mode="native"))
+
+
+def test_empty_and_degenerate():
+    for dt in (np.float64, np.int32):
+        a = np.zeros((3, 0), dtype=dt)
+        b = np.zeros((0, 5), dtype=dt)
+        folds = FOLD_I if dt == np.int32 else FOLD_F
+        for op1 in folds:
+            say("K=0", op1)
+            d = host(moa.inner(gpu(a), gpu(b), op1, "add"))
+            eq(d, np.full((3, 5), oracle.identity_of(op1, dt), dtype=dt))
+        assert moa.inner(gpu(np.zeros((0, 4), dt)), gpu(np.ones((4, 3), dt))).shape == (0, 3)
+    d = host(moa.inner_split(gpu(np.zeros((3, 0))), gpu(np.zeros((0, 2)))))
+    eq(d, np.zeros((3, 2)))
+    c = host(moa.outer(gpu(np.array(3.0)), gpu(np.array(4.0)), "sub"))
+    assert c.shape == () and c == -1.0
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32, np.int32])
+def test_outer_all_ops_bit_exact(dt):
+    rng = np.random.default_rng(102)
+    elems = ELEM_I if dt == np.int32 else ELEM_F
+    for sa, sb in [((), (5,)), ((3, 2), (7,)), ((17, 3), (2, 129)), ((4,), (1024,)), ((5, 5), (300, 3))]:
+        a = rand(rng, sa, dt)
+        b = rand(rng, sb, dt)
+        for op in elems:
+            say("outer", np.dtype(dt).name, sa, sb, op)
+            eq(host(moa.outer(gpu(a), gpu(b), op)), oracle.outer(a, b, op))
+
+
+@pytest.mark.parametrize("dt,tol", [(np.float64, 1e-13), (np.float32, 1e-5)])
+def test_mfma_plus_times(dt, tol):
+    rng = np.random.default_rng(103)
+    for sa, sb in [((37, 19), (19, 53)), ((2, 3, 70), (70, 5, 9)), ((257, 130), (130, 129)), ((640, 333), (333, 512)),
+                   ((9,), (9, 4))]:
+        a = mi.uniform_f64(rng, sa).astype(dt)
+        b = mi.uniform_f64(rng, sb).astype(dt)
+        say("mfma", np.dtype(dt).name, sa, sb)
+        d = host(moa.inner(gpu(a), gpu(b)))
+        ref = oracle.inner_dot2(a, b)
+        assert nerr(d, ref) <= tol, nerr(d, ref)
+
+
+def test_mfma_f64_exact_integers():
+    # Integer entries with |x| <= 8 and K <= 8192: every partial sum is exact,
+    # so any summation order gives the exact product.
+    rng = np.random.default_rng(104)
+    a = mi.small_int_f64(rng, (200, 1000), 8)
+    b = mi.small_int_f64(rng, (1000, 130), 8)
+    say("mfma exact ints")
+    eq(host(moa.inner(gpu(a), gpu(b))), (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads, sampled rows.
+
+def _sample_rows(rng, m, n=24):
+    rows = np.unique(np.concatenate([[0, m - 1], rng.integers(0, m, n)]))
+    return rows
+
+
+def test_small_mixed_full():
+    a, b, oa, ob = mi.workload_small_mixed()
+    say("512^3 fp64 + outer 32x32 o 16x16")
+    d = host(moa.inner(gpu(a), gpu(b)))
+    assert nerr(d, oracle.inner_dot2(a, b)) <= 1e-13
+    eq(host(moa.outer(gpu(oa), gpu(ob), "mul")), oracle.outer(oa, ob, "mul"))
+
+
+def test_rank_general_fp64_full_sampled():
+    a, b = mi.workload_rank_general_f64()
+    say("rank-5 fp64", a.shape, b.shape)
+    ga, gb = gpu(a), gpu(b)
+    d = moa.inner(ga, gb)
+    assert tuple(d.shape) == (64, 64, 32, 128, 64)
+    m = 64 * 64 * 32
+    rows = _sample_rows(np.random.default_rng(5), m)
+    dflat = d.reshape(m, -1)
+    got = host(dflat[torch.from_numpy(rows).to(DEV)])
+    ref = oracle.inner_dot2(a, b, rows=rows).reshape(len(rows), -1)
+    assert nerr(got, ref) <= 1e-13
+    del d, dflat
+    torch.cuda.empty_cache()
+
+
+def test_tropical_full_sampled():
+    a, b = mi.workload_tropical()
+    say("tropical 2048^3 (max,+)")
+    d = moa.inner(gpu(a), gpu(b), "max", "add")
+    rows = _sample_rows(np.random.default_rng(6), 2048, 64)
+    got = host(d[torch.from_numpy(rows).to(DEV)])
+    eq(got, oracle.inner(a, b, "max", "add", rows=rows))
+
+
+def test_outer_f32_full_sampled():
+    a, b = mi.workload_outer_f32()
+    say("outer fp32 (-) <512 512> o <64 64>")
+    c = moa.outer(gpu(a), gpu(b), "sub")
+    assert tuple(c.shape) == (512, 512, 64, 64)
+    rows = _sample_rows(np.random.default_rng(7), 512 * 512, 64)
+    got = host(c.reshape(512 * 512, -1)[torch.from_numpy(rows).to(DEV)])
+    eq(got, oracle.outer(a.reshape(-1)[rows], b.reshape(-1), "sub"))
+    del c
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# Split precision.
+
+@pytest.mark.parametrize("shape", [(100, 300, 70), (64, 64, 128), (1, 1, 1), (257, 1000, 131), (33, 65, 200)])
+def test_split_matches_oracle_scheme(shape):
+    M, K, N = shape
+    rng = np.random.default_rng(105)
+    a = mi.scaled_f64(rng, (M, K))
+    b = mi.scaled_f64(rng, (K, N))
+    ref = oracle.inner_dot2(a, b)
+    for S in range(1, 8):
+        say("split", shape, "S", S)
+        d = host(moa.inner_split(gpu(a), gpu(b), "bf16", S))
+        want = oracle.split_inner(a, b, nslices=S, beta=9)
+        assert nerr(d, want) <= 1e-14, (S, nerr(d, want))
+        if S >= 5:
+            assert nerr(d, ref) <= 1e-12, (S, nerr(d, ref))
+
+
+def test_split_exact_cases():
+    rng = np.random.default_rng(106)
+    # Integers in [-255, 255] with a row/column maximum in [128, 256) are one
+    # signed 9-bit digit each: one slice gives the exact product.
+    a = mi.small_int_f64(rng, (70, 400), 255)
+    b = mi.small_int_f64(rng, (400, 90), 255)
+    a[:, 0] = 200.0
+    b[0, :] = -200.0
+    say("split exact integers")
+    d = host(moa.inner_split(gpu(a), gpu(b), "bf16", 1))
+    eq(d, (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
+    # Power-of-two row/column scaling commutes exactly with the scheme.
+    a = mi.scaled_f64(rng, (40, 300))
+    b = mi.scaled_f64(rng, (300, 50))
+    d = host(moa.inner_split(gpu(a), gpu(b), "bf16", 5))
+    a2 = a.copy()
+    a2[7] = np.ldexp(a2[7], 11)
+    d2 = host(moa.inner_split(gpu(a2), gpu(b), "bf16", 5))
+    want = d.copy()
+    want[7] = np.ldexp(want[7], 11)
+    eq(d2, want)
+
+
+def test_split_full_size_sampled():
+    a, b = mi.workload_split()
+    say("split 8192^3 S=5")
+    d = moa.inner_split(gpu(a), gpu(b), "bf16", 5)
+    rows = _sample_rows(np.random.default_rng(8), 8192, 14)
+    got = host(d[torch.from_numpy(rows).to(DEV)])
+    ref = oracle.inner_dot2(a, b, rows=rows)
+    e = nerr(got, ref)
+    say("split 8192^3 err vs Dot2 %.3e" % e)
+    assert e <= 1e-12
+    want = oracle.split_inner(a, b, nslices=5, beta=9, rows=rows[:6])
+    assert nerr(got[:6], want) <= 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Differentiation.
+
+def test_grad_finite_differences_fp64():
+    rng = mi.rng_for(mi.DIFFERENTIATION, salt=1)
+    a = mi.uniform_f64(rng, (4, 4, 8))
+    b = mi.uniform_f64(rng, (8, 4, 4))
+    g = mi.uniform_f64(rng, (4, 4, 4, 4))
+    say("grad FD 4x4x8 . 8x4x4")
+    da, db = moa.inner_grad(gpu(a), gpu(b), gpu(g))
+    da, db = host(da), host(db)
+    gb, gg = gpu(b), gpu(g)
+    h = 2.0 ** -8
+
+    def loss(x, y):
+        return float(torch.sum(moa.inner(gpu(x), gpu(y)) * gg).item())
+
+    fa = np.zeros_like(a)
+    for idx in np.ndindex(a.shape):
+        ap, am = a.copy(), a.copy()
+        ap[idx] += h
+        am[idx] -= h
+        fa[idx] = (loss(ap, b) - loss(am, b)) / (2 * h)
+    fb = np.zeros_like(b)
+    for idx in np.ndindex(b.shape):
+        bp, bm = b.copy(), b.copy()
+        bp[idx] += h
+        bm[idx] -= h
+        fb[idx] = (loss(a, bp) - loss(a, bm)) / (2 * h)
+    # L is linear in each element, so central differences are exact up to rounding.
+    assert np.max(np.abs(fa - da)) <= 1e-12
+    assert np.max(np.abs(fb - db)) <= 1e-12
+
+
+def test_grad_full_size_vs_oracle():
+    a, b, g = mi.workload_grad()
+    say("grad fp32 <32 128 512> . <512 64 64>")
+    ta = gpu(a).requires_grad_(True)
+    tb = gpu(b).requires_grad_(True)
+    d = moa.moa_inner(ta, tb)
+    d.backward(gpu(g))
+    da, db = host(ta.grad), host(tb.grad)
+    # dA = G (+,*) B_rot, B_rot = B with its first axis moved last;
+    # dB = A_rot (+,*) G, A_rot = A with its last axis moved first.
+    b_rot = np.ascontiguousarray(np.moveaxis(b, 0, -1))
+    a_rot = np.ascontiguousarray(np.moveaxis(a, -1, 0))
+    g2 = g.reshape(32, 128, 64 * 64)
+    ref_da = oracle.inner(g2, b_rot.reshape(64 * 64, 512)).reshape(a.shape)
+    ref_db = oracle.inner(a_rot.reshape(512, 32 * 128), g.reshape(32 * 128, 64, 64)).reshape(b.shape)
+    assert nerr(da, ref_da) <= 1e-5
+    assert nerr(db, ref_db) <= 1e-5
+    assert nerr(host(d.detach()), oracle.inner(a, b)) <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Batching.
+
+def _check_batch(probs, ds, idx):
+    for i in idx:
+        p = probs[i]
+        got = ds[i]
+        ref = oracle.inner(p.a, p.b)
+        e = nerr(got, ref)
+        assert e <= 1e-5, (i, p.shape_a, p.shape_b, e)
+
+
+def test_batch_small_full_check():
+    probs = mi.batch_problems(mi.rng_for(mi.BATCH, salt=1), 600)
+    As = [gpu(p.a) for p in probs]
+    Bs = [gpu(p.b) for p in probs]
+    Ds = [torch.full(moa.inner_shape(p.shape_a, p.shape_b), float("nan"), device=DEV) for p in probs]
+    say("batch 600")
+    bt = moa.Batch(As, Bs, Ds)
+    items, launches = bt.info()
+    assert launches == 1 and items >= 600
+    for rep in range(3):
+        for d in Ds:
+            d.fill_(float("nan"))
+        bt.run()
+        torch.cuda.synchronize()
+        hd = [d.cpu().numpy() for d in Ds]
+        _check_batch(probs, hd, range(len(probs)))
+    bt.close()
+
+
+def test_batch_full_size_sampled():
+    probs = mi.batch_problems(mi.rng_for(mi.BATCH), 10000)
+    As = [gpu(p.a) for p in probs]
+    Bs = [gpu(p.b) for p in probs]
+    Ds = [torch.empty(moa.inner_shape(p.shape_a, p.shape_b), device=DEV) for p in probs]
+    say("batch 10000")
+    bt = moa.Batch(As, Bs, Ds)
+    bt.run()
+    bt.run()
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(9).choice(len(probs), 400, replace=False)
+    _check_batch(probs, {int(i): Ds[int(i)].cpu().numpy() for i in idx}, [int(i) for i in idx])
+    bt.close()
+
+
+def test_batch_autotune_then_build():
+    say("batch autotune")
+    table = moa.batch_autotune(torch.float32, reps=2)
+    assert len(table.strip().splitlines()) == 8
+    probs = mi.batch_problems(mi.rng_for(mi.BATCH, salt=2), 200)
+    As = [gpu(p.a) for p in probs]
+    Bs = [gpu(p.b) for p in probs]
+    Ds = [torch.empty(moa.inner_shape(p.shape_a, p.shape_b), device=DEV) for p in probs]
+    bt = moa.Batch(As, Bs, Ds)
+    bt.run()
+    torch.cuda.synchronize()
+    _check_batch(probs, [d.cpu().numpy() for d in Ds], range(len(probs)))
+    bt.close()
+
+
+def test_errors_on_device_tensors():
+    a = gpu(np.ones((3, 4)))
+    b = gpu(np.ones((5, 2)))
+    with pytest.raises(moa.MoaError) as e:
+        moa.inner(a, b)
+    assert moa.STATUS[e.value.status] == "MOA_ERR_SHAPE"
+    with pytest.raises(moa.MoaError) as e:
+        moa.inner(a, gpu(np.ones((4, 2))), "sub", "mul")
+    assert moa.STATUS[e.value.status] == "MOA_ERR_OP"
