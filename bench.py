@@ -62,18 +62,19 @@ def cpu_baseline(a, b, target_s=12.0):
     import oracle
     K = a.shape[1]
     N = b.shape[1]
-    rows = [0]
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    # Calibrate on one row per thread (the oracle parallelises over rows).
+    rows = list(range(cores))
     t0 = time.perf_counter()
     oracle.inner(a, b, rows=rows)
     t1 = time.perf_counter() - t0
-    nrows = max(1, min(a.shape[0], int(target_s / max(t1, 1e-3))))
+    nrows = max(cores, min(a.shape[0], int(cores * target_s / max(t1, 1e-3)) // cores * cores))
     rng = np.random.default_rng(1234)
     rows = np.sort(rng.choice(a.shape[0], nrows, replace=False))
     t0 = time.perf_counter()
     oracle.inner(a, b, rows=rows)
     dt = time.perf_counter() - t0
     ops = 2.0 * nrows * K * N
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
     return {"value": ops / dt / 1e9, "unit": "Gop/s", "cores": cores, "kind": "oracle",
             "sample": "%d of 8192 result rows (%.3g ops, %.1f s), plain FP64 fold of the psi definition" %
                       (nrows, ops, dt)}

@@ -35,7 +35,8 @@ def say(*a):
 
 
 def gpu(x):
-    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    # np.asarray keeps 0-d arrays 0-d (ascontiguousarray would make them 1-d).
+    return torch.from_numpy(np.asarray(x, order="C")).to(DEV)
 
 
 def host(t):
