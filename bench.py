@@ -33,7 +33,7 @@ METRIC = "inner-product Gop/s at 8192^3: split-BF16 vs plain FP64, at ≤1e-12 r
 PEAK_BF16_TFLOPS = 2516.6
 PEAK_FP64_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "split_gemm_8192_traffic.json")
-SPLIT_SRC = os.path.join(ROOT, "paper_0907_0792_amd", "csrc", "k_split.hip")
+SPLIT_SRCS = [os.path.join(ROOT, "paper_0907_0792_amd", "csrc", f) for f in ("k_split.hip", "split_gemm.hpp")]
 
 
 def log(*a):
@@ -41,7 +41,10 @@ def log(*a):
 
 
 def kernel_hash():
-    return hashlib.sha256(open(SPLIT_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in SPLIT_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profiles(launch_flops):
@@ -89,6 +92,8 @@ def main():
     ap.add_argument("--slices", type=int, default=5)
     ap.add_argument("--plain-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).", flush=True)
@@ -98,6 +103,17 @@ def main():
     import torch
     import moa_inputs as mi
     import paper_0907_0792_amd as moa
+
+    if args.calibrate_copy:
+        # A plain copy of known size: HBM counters of this dispatch scale the
+        # counters of the other kernels (bytes counted per byte moved).
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of %d bytes x2 done" % src.numel())
+        del src, dst
 
     n = args.size
     S = args.slices

@@ -12,13 +12,10 @@
 // the same weight 2^-(16 + 9 d), so they share one FP32 accumulator per level:
 //     D_ij = 2^(e_i + f_j - 16) * sum_d 2^-9d T_d[i, j],
 //     T_d = sum_{s+t=d} sigma^A_s . sigma^B_t   (integer-valued).
-// Products of digits are at most 2^16; a level-d accumulator receives at most
-// (d+1) * 64 * 2^16 <= 2^24 in magnitude over a period of 64 k values for
-// d <= 3, so its FP32 sum is exact; it is then folded into an FP64
-// accumulator and restarted (levels >= 4 weigh at most 2^-52 of a level-0 unit
-// and their FP32 rounding is far below FP64 rounding). Within one period the
-// levels 0..3 combine exactly in FP64 (they span 51 bits), so each period adds
-// one rounded FP64 term per output.
+// Products of digits are at most 2^16, so an FP32 level accumulator is exact
+// over a bounded number of k values; the product kernel (split_gemm.hpp) folds
+// each level into FP64 within that bound and scales back by 2^(e_i + f_j) at
+// the end.
 //
 // Data layout. Slices are written once, in the operand layout of
 // v_mfma_f32_32x32x16_bf16: a "chunk" is the 32 x 16 (A) or 16 x 32 (B)
@@ -28,29 +25,32 @@
 // row block are one contiguous run. The product kernel copies runs straight
 // into LDS with global_load_lds_dwordx4 (no staging registers) and each wave
 // reads a fragment back as one conflict-free ds_read_b128.
+//
+// This file holds the row/column scans, the slicing kernels and the launch
+// plan; the product kernel is in split_gemm.hpp.
 #include "common.hpp"
 #include "internal.hpp"
+#include "split_gemm.hpp"
 
 namespace moa {
 
 namespace {
 
-constexpr int kBeta = 9;               // BF16 digit width (|digit| <= 2^(beta-1) = 256)
-constexpr int kFlushK = 64;            // exact-accumulation period in k
-// 16-wide k blocks per LDS stage (two, unless the slices would overflow LDS).
-template <int S>
-constexpr int stage_kb() { return S <= 6 ? 2 : 1; }
-constexpr int kSplitBM = 64;           // workgroup tile rows (2 waves x 32)
-constexpr int kSplitWN = 2;            // 32-wide column blocks per wave
-constexpr int kSplitBN = 64 * kSplitWN;  // workgroup tile columns (2 waves)
+using split::exponent_of_max;
+using split::kBeta;
+constexpr int kFlushK = 64;  // K is padded to a multiple of this
 
-__device__ __forceinline__ int exponent_of_max(uint64_t bits) {
-  // bits: IEEE pattern of a non-negative double. frexp exponent, 0 for 0.
-  const double m = __longlong_as_double((long long)bits);
-  if (m == 0.0) return 0;
-  int e;
-  (void)frexp(m, &e);
-  return e;
+// Workgroup layout of the slice-pair kernel by slice count: 2 x 4 waves of
+// 32 x 32 (64 x 128 tile) while four LDS stages of it fit, else 2 x 2 waves.
+template <int S>
+struct Layout {
+  static constexpr int WMW = 2, WNW = (S <= 6) ? 4 : 2, WN = 1;
+  using C = split::Cfg<S, WMW, WNW, WN>;
+};
+
+static void tile_of(int S, int *bm, int *bn) {
+  *bm = 64;
+  *bn = (S <= 6) ? 128 : 64;
 }
 
 // Row maxima of |A| (M x K row-major): one wave per row; IEEE bit pattern out.
@@ -145,142 +145,6 @@ __global__ __launch_bounds__(256) void k_slice_b(const double *__restrict__ B, i
   for (int s = 0; s < S; ++s) dst[s * 64] = sig[s];
 }
 
-__device__ __forceinline__ floatx16 mfma_bf16(const bf16x8 &a, const bf16x8 &b, const floatx16 &c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-}
-
-// The fused slice-pair product. Workgroup = 4 waves (2 x 2) owning a
-// 64 x 128 tile of D; each wave a 32 x 64 block (two 32 x 32 accumulators per
-// level).
-template <int S>
-__global__ __launch_bounds__(256, 1) void k_split_gemm(const bf16x8 *__restrict__ Apk, const bf16x8 *__restrict__ Bpk,
-                                                       const uint64_t *__restrict__ rowmax,
-                                                       const uint64_t *__restrict__ colmax, double *__restrict__ D,
-                                                       int64_t M, int64_t N, int64_t KB, int64_t tiles_m,
-                                                       int64_t tiles_n) {
-  constexpr int WN = kSplitWN;
-  constexpr int kStageKB = stage_kb<S>();
-  constexpr int MBW = kSplitBM / 32;      // row blocks per workgroup
-  constexpr int NBW = kSplitBN / 32;      // column blocks per workgroup
-  constexpr int A_CH = MBW * kStageKB * S;  // chunks of A per stage
-  constexpr int B_CH = NBW * kStageKB * S;
-  constexpr int ST_CH = A_CH + B_CH;
-  constexpr int PER_WAVE = ST_CH / 4;           // copies every wave issues
-  constexpr int MAX_WAVE = (ST_CH + 3) / 4;     // copies the first waves issue
-  constexpr int STAGES_PER_FLUSH = kFlushK / (16 * kStageKB);
-  __shared__ bf16x8 lds[2][ST_CH * 64];
-
-  int64_t tm, tn;
-  grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 4, tm, tn);
-  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  const int wm = wave / 2, wn = wave % 2;
-
-  // Chunk c of a stage: A chunks first ([mb][kb][s]), then B ([nb][kb][s]).
-  auto issue_stage = [&](int64_t st, int buf) {
-#pragma unroll
-    for (int q = 0; q < MAX_WAVE; ++q) {
-      const int c = wave + 4 * q;
-      if (c >= ST_CH) break;
-      const bf16x8 *src;
-      if (c < A_CH) {
-        const int mbl = c / (kStageKB * S), rest = c % (kStageKB * S);
-        src = Apk + (((tm * MBW + mbl) * KB + st * kStageKB) * S + rest) * 64;
-      } else {
-        const int cb = c - A_CH;
-        const int nbl = cb / (kStageKB * S), rest = cb % (kStageKB * S);
-        src = Bpk + (((tn * NBW + nbl) * KB + st * kStageKB) * S + rest) * 64;
-      }
-      __builtin_amdgcn_global_load_lds((const void *)(src + lane), (__attribute__((address_space(3))) void *)&lds[buf][c * 64], 16, 0, 0);
-    }
-  };
-
-  floatx16 acc[S][WN];
-  double acc64[WN][16];
-#pragma unroll
-  for (int j = 0; j < WN; ++j)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc64[j][v] = 0.0;
-#pragma unroll
-  for (int d = 0; d < S; ++d)
-#pragma unroll
-    for (int j = 0; j < WN; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[d][j][v] = 0.0f;
-
-  const int64_t nstages = KB / kStageKB;
-  issue_stage(0, 0);
-  for (int64_t st = 0; st < nstages; ++st) {
-    const int buf = (int)(st & 1);
-    if (st + 1 < nstages) {
-      issue_stage(st + 1, buf ^ 1);
-      // Wait for this stage's copies; up to PER_WAVE of the next stage stay in
-      // flight (a wave that issued one more waits for one of those too).
-      __builtin_amdgcn_s_waitcnt(0x0F70 | PER_WAVE);
-    } else {
-      __builtin_amdgcn_s_waitcnt(0x0F70);
-    }
-    // Plain barrier, not __syncthreads(): its fence would also wait for the
-    // next stage's copies. LDS is coherent within the workgroup, and each
-    // wave has already waited for its own copies of this stage above.
-    __builtin_amdgcn_s_barrier();
-#pragma unroll
-    for (int kbl = 0; kbl < kStageKB; ++kbl) {
-      bf16x8 af[S], bfr[S][WN];
-#pragma unroll
-      for (int s = 0; s < S; ++s) af[s] = lds[buf][((wm * kStageKB + kbl) * S + s) * 64 + lane];
-#pragma unroll
-      for (int t = 0; t < S; ++t)
-#pragma unroll
-        for (int j = 0; j < WN; ++j)
-          bfr[t][j] = lds[buf][A_CH * 64 + (((wn * WN + j) * kStageKB + kbl) * S + t) * 64 + lane];
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int t = 0; t + s < S; ++t)
-#pragma unroll
-          for (int j = 0; j < WN; ++j) acc[s + t][j] = mfma_bf16(af[s], bfr[t][j], acc[s + t][j]);
-    }
-    if ((st + 1) % STAGES_PER_FLUSH == 0 || st + 1 == nstages) {
-      // Fold the period into FP64: sum_d 2^-9d T_d, innermost (smallest) first.
-#pragma unroll
-      for (int j = 0; j < WN; ++j)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          double p = (double)acc[S - 1][j][v];
-#pragma unroll
-          for (int d = S - 2; d >= 0; --d) p = fma(p, 0x1p-9, (double)acc[d][j][v]);
-          acc64[j][v] += p;
-        }
-#pragma unroll
-      for (int d = 0; d < S; ++d)
-#pragma unroll
-        for (int j = 0; j < WN; ++j)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) acc[d][j][v] = 0.0f;
-    }
-    // Every wave is done reading `buf` before the next iteration refills it.
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-    __builtin_amdgcn_s_barrier();
-  }
-
-  // Epilogue: exact power-of-two descaling, D[i, j] = 2^(e_i + f_j - 16) * acc.
-  const int64_t col_base = tn * kSplitBN + wn * (32 * WN);
-  const int64_t row_base = tm * kSplitBM + wm * 32;
-#pragma unroll
-  for (int j = 0; j < WN; ++j) {
-    const int64_t gn = col_base + j * 32 + lane % 32;
-    const int fe = (gn < N) ? exponent_of_max(colmax[gn]) : 0;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t gm = row_base + (v / 4) * 8 + (lane / 32) * 4 + (v % 4);
-      if (gm < M && gn < N) {
-        const int ee = exponent_of_max(rowmax[gm]);
-        D[gm * N + gn] = ldexp(acc64[j][v], ee + fe - 2 * (kBeta - 1));
-      }
-    }
-  }
-}
-
 template <int S>
 hipError_t launch_prepare_s(const SplitPlan &p, const double *A, const double *B, void *ws, hipStream_t s) {
   char *w = (char *)ws;
@@ -310,9 +174,10 @@ hipError_t launch_multiply_s(const SplitPlan &p, double *D, void *ws, hipStream_
   const bf16x8 *Apk = (const bf16x8 *)(w + p.off_ap);
   const bf16x8 *Bpk = (const bf16x8 *)(w + p.off_bp);
   const int64_t KB = p.Kp / 16;
-  const int64_t tmn = p.Mp / kSplitBM, tnn = p.Np / kSplitBN;
-  hipLaunchKernelGGL((k_split_gemm<S>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, Apk, Bpk, rowmax, colmax, D,
-                     p.M, p.N, KB, tmn, tnn);
+  using L = Layout<S>;
+  const int64_t tmn = p.Mp / L::C::BM, tnn = p.Np / L::C::BN;
+  hipLaunchKernelGGL((split::k_split_gemm<S, L::WMW, L::WNW, L::WN, 1>), dim3((unsigned)(tmn * tnn)),
+                     dim3(L::C::kThreads), 0, s, Apk, Bpk, rowmax, colmax, D, p.M, p.N, KB, tmn, tnn);
   return hipGetLastError();
 }
 
@@ -329,8 +194,10 @@ bool split_plan(int64_t M, int64_t K, int64_t N, int fmt, int S, SplitPlan *p) {
   p->fmt = fmt;
   p->S = S;
   p->beta = kBeta;
-  p->Mp = round_up(M > 0 ? M : 1, kSplitBM);
-  p->Np = round_up(N > 0 ? N : 1, kSplitBN);
+  int bm, bn;
+  tile_of(S, &bm, &bn);
+  p->Mp = round_up(M > 0 ? M : 1, bm);
+  p->Np = round_up(N > 0 ? N : 1, bn);
   p->Kp = round_up(K > 0 ? K : 1, kFlushK);
   size_t off = 0;
   p->off_ea = off;
