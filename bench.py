@@ -15,6 +15,13 @@ launch / its average HIP-event duration, against 2516.6 TFLOP/s dense BF16),
 and the CPU oracle timed on a bounded sample of rows.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Other rows of the hot path are measured with --workload (one JSON line each,
+same fields, their own roofline): plain64 (FP64 (+,*) 8192^3), rank5 (FP64
+(+,*) <64 64 32 256>.<256 128 64>), tropical (int32 (max,+) 2048^3), outer
+(FP32 (-) <512 512> o <64 64>), batch (10,000 uneven FP32 products, one graph
+launch), grad (FP32 forward + backward <32 128 512>.<512 64 64>), small
+(FP64 512^3 plus the <32 32> o <16 16> outer product).
 """
 from __future__ import annotations
 
@@ -32,6 +39,10 @@ sys.path.insert(0, ROOT)
 METRIC = "inner-product Gop/s at 8192^3: split-BF16 vs plain FP64, at ≤1e-12 rel err"
 PEAK_BF16_TFLOPS = 2516.6
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+# Non-packed 32-bit VALU: 256 CUs x 64 lanes x 2.4 GHz.
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "split_gemm_8192_traffic.json")
 SPLIT_SRCS = [os.path.join(ROOT, "paper_0907_0792_amd", "csrc", f) for f in ("k_split.hip", "split_gemm.hpp")]
 
@@ -83,6 +94,137 @@ def cpu_baseline(a, b, target_s=12.0):
                       (nrows, ops, dt)}
 
 
+def _time_events(fn, steps, warmup):
+    """Average ms of fn() over `steps` runs, HIP events on the current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def other_workload(args):
+    """One JSON line for a non-headline row of the hot path."""
+    import numpy as np
+    import torch
+    import moa_inputs as mi
+    import paper_0907_0792_amd as moa
+    dev = torch.device("cuda:0")
+    w = args.workload
+    base = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "data": "synthetic"}
+
+    def put(x):
+        return torch.from_numpy(np.asarray(x, order="C")).to(dev)
+
+    if w in ("plain64", "rank5", "small"):
+        if w == "plain64":
+            a_h, b_h = mi.workload_split(m=args.size, k=args.size, n=args.size)
+            desc = "FP64 (+,*) %d^3, entries u*2^k" % args.size
+        elif w == "rank5":
+            a_h, b_h = mi.workload_rank_general_f64()
+            desc = "FP64 (+,*) <64 64 32 256> . <256 128 64> -> <64 64 32 128 64>, U[-1,1]"
+        else:
+            a_h, b_h, oa_h, ob_h = mi.workload_small_mixed()
+            desc = "FP64 (+,*) 512^3 plus FP64 (*) outer <32 32> o <16 16>, U[-1,1]"
+        a, b = put(a_h), put(b_h)
+        out = torch.empty(moa.inner_shape(a.shape, b.shape), dtype=torch.float64, device=dev)
+        M = int(np.prod(a_h.shape[:-1]))
+        K = a_h.shape[-1]
+        N = int(np.prod(b_h.shape[1:]))
+        if w == "small":
+            oa, ob = put(oa_h), put(ob_h)
+            oc = torch.empty(tuple(oa.shape) + tuple(ob.shape), dtype=torch.float64, device=dev)
+            fn = lambda: (moa.inner(a, b, out=out), moa.outer(oa, ob, "mul", out=oc))
+        else:
+            fn = lambda: moa.inner(a, b, out=out)
+        ms, wall = _time_events(fn, args.steps, args.warmup)
+        flops = 2.0 * M * N * K
+        t = flops / (ms * 1e-3) / 1e12
+        return dict(base, metric="inner-product Gop/s (%s)" % w, value=round(flops / (ms * 1e-3) / 1e9, 3),
+                    unit="Gop/s", ms_per_step=round(ms, 4), dtype="f64",
+                    config={"workload": desc, "m": M, "k": K, "n": N},
+                    roofline={"bound": "mfma", "kernel": "k_gemm<double>", "achieved": round(t, 3),
+                              "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(t / PEAK_FP64_TFLOPS, 4),
+                              "traffic": None})
+    if w == "tropical":
+        a_h, b_h = mi.workload_tropical()
+        a, b = put(a_h), put(b_h)
+        out = torch.empty((2048, 2048), dtype=torch.int32, device=dev)
+        ms, wall = _time_events(lambda: moa.inner(a, b, "max", "add", out=out), args.steps, args.warmup)
+        terms = 2048.0 ** 3
+        ops = 2 * terms  # one add and one max per term
+        t = ops / (ms * 1e-3) / 1e12
+        return dict(base, metric="tropical (max,+) inner product Gop/s", value=round(ops / (ms * 1e-3) / 1e9, 3),
+                    unit="Gop/s", ms_per_step=round(ms, 4), dtype="i32",
+                    config={"workload": "int32 (max,+) 2048^3, U{-1000..1000}", "m": 2048, "k": 2048, "n": 2048},
+                    roofline={"bound": "alu", "kernel": "k_simt_inner<int,max,add,4,4>", "achieved": round(t, 3),
+                              "peak": round(PEAK_VALU_TOPS, 2), "unit": "Tlane-op/s",
+                              "frac": round(t / PEAK_VALU_TOPS, 4), "traffic": None})
+    if w == "outer":
+        a_h, b_h = mi.workload_outer_f32()
+        a, b = put(a_h), put(b_h)
+        out = torch.empty((512, 512, 64, 64), dtype=torch.float32, device=dev)
+        ms, wall = _time_events(lambda: moa.outer(a, b, "sub", out=out), args.steps, args.warmup)
+        nbytes = out.numel() * 4 + (a.numel() + b.numel()) * 4
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return dict(base, metric="outer product GB/s", value=round(gbs, 2), unit="GB/s", ms_per_step=round(ms, 4),
+                    dtype="f32", config={"workload": "FP32 (-) outer <512 512> o <64 64> -> 2^30 elements"},
+                    roofline={"bound": "hbm", "kernel": "k_outer_vec<float,sub>", "achieved": round(gbs, 2),
+                              "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                              "traffic": None})
+    if w == "batch":
+        probs = mi.batch_problems(mi.rng_for(mi.BATCH), 10000)
+        As = [put(p.a) for p in probs]
+        Bs = [put(p.b) for p in probs]
+        Ds = [torch.empty(moa.inner_shape(p.shape_a, p.shape_b), device=dev) for p in probs]
+        bt = moa.Batch(As, Bs, Ds)
+        ms, wall = _time_events(bt.run, args.steps, args.warmup)
+        items, launches = bt.info()
+        flops = sum(2.0 * np.prod(p.a.shape) * np.prod(p.b.shape[1:]) for p in probs)
+        nbytes = sum(4.0 * (p.a.size + p.b.size + np.prod(p.a.shape[:-1]) * np.prod(p.b.shape[1:])) for p in probs)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        bt.close()
+        return dict(base, metric="batched inner products Gop/s", value=round(flops / (ms * 1e-3) / 1e9, 3),
+                    unit="Gop/s", ms_per_step=round(ms, 4), dtype="f32",
+                    config={"workload": "10,000 uneven FP32 (+,*) products, one persistent graph launch",
+                            "problems": len(probs), "work_items": items, "launches": launches,
+                            "flops": flops, "bytes": nbytes},
+                    roofline={"bound": "hbm", "kernel": "k_batch<float>", "achieved": round(gbs, 2),
+                              "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                              "traffic": None})
+    if w == "grad":
+        a_h, b_h, g_h = mi.workload_grad()
+        a = put(a_h).requires_grad_(True)
+        b = put(b_h).requires_grad_(True)
+        g = put(g_h)
+
+        def fb():
+            a.grad = None
+            b.grad = None
+            d = moa.moa_inner(a, b)
+            d.backward(g)
+        ms, wall = _time_events(fb, args.steps, args.warmup)
+        flops = 3 * 2.0 * (32 * 128) * 512 * (64 * 64)
+        t = flops / (ms * 1e-3) / 1e12
+        return dict(base, metric="forward+backward Gop/s", value=round(flops / (ms * 1e-3) / 1e9, 3), unit="Gop/s",
+                    ms_per_step=round(ms, 4), dtype="f32",
+                    config={"workload": "FP32 (+,*) <32 128 512> . <512 64 64>, forward + dA + dB"},
+                    roofline={"bound": "mfma", "kernel": "k_gemm<float>", "achieved": round(t, 3),
+                              "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(t / PEAK_FP32_TFLOPS, 4),
+                              "traffic": None})
+    raise ValueError(w)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +234,8 @@ def main():
     ap.add_argument("--slices", type=int, default=5)
     ap.add_argument("--plain-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="split",
+                    choices=["split", "plain64", "rank5", "tropical", "outer", "batch", "grad", "small"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -114,6 +258,10 @@ def main():
         torch.cuda.synchronize()
         log("bench: calibration copy of %d bytes x2 done" % src.numel())
         del src, dst
+
+    if args.workload != "split":
+        print(json.dumps(other_workload(args)), flush=True)
+        return
 
     n = args.size
     S = args.slices
