@@ -327,7 +327,43 @@ def main():
     diff = float(torch.linalg.norm(d[rows] - dp[rows]) / torch.linalg.norm(dp[rows]))
     log("bench: plain %.3f ms, %.1f Gop/s; split/plain %.3fx; rel diff %.2e" %
         (plain_ms, plain_gops, value / plain_gops, diff))
-    del dp
+
+    # The INT8-slice variant on the same inputs (7 slices of 7-bit digits).
+    S8 = 7
+    ws8 = torch.empty(moa.split_workspace_bytes(a.shape, b.shape, "int8", S8), dtype=torch.uint8, device=dev)
+    d8 = torch.empty_like(d)
+
+    def step8(ev=None):
+        if ev is not None:
+            ev[0].record()
+        moa.split_prepare(a, b, ws8, "int8", S8)
+        if ev is not None:
+            ev[1].record()
+        moa.split_multiply(a.shape, b.shape, d8, ws8, "int8", S8)
+        if ev is not None:
+            ev[2].record()
+
+    for _ in range(max(1, args.warmup)):
+        step8()
+    torch.cuda.synchronize()
+    evs8 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step8(evs8[i])
+    torch.cuda.synchronize()
+    el8 = time.perf_counter() - t0
+    mult8 = sum(e[1].elapsed_time(e[2]) for e in evs8) / args.steps
+    prep8 = sum(e[0].elapsed_time(e[1]) for e in evs8) / args.steps
+    diff8 = float(torch.linalg.norm(d8[rows] - dp[rows]) / torch.linalg.norm(dp[rows]))
+    int8_ops = S8 * (S8 + 1) // 2 * ops / (mult8 * 1e-3) / 1e12
+    split_int8 = {"value": round(ops * args.steps / el8 / 1e9, 3), "unit": "Gop/s",
+                  "ms_per_step": round(el8 * 1e3 / args.steps, 4),
+                  "stages_ms": {"prepare": round(prep8, 4), "multiply": round(mult8, 4)},
+                  "slices": S8, "slice_pairs": S8 * (S8 + 1) // 2, "rel_diff_vs_plain": diff8,
+                  "product_kernel_tops": round(int8_ops, 2), "frac_int8_peak": round(int8_ops / 5033.2, 4)}
+    log("bench: int8 split %.3f ms/step, %.1f Gop/s, rel diff %.2e" %
+        (split_int8["ms_per_step"], split_int8["value"], diff8))
+    del dp, d8, ws8
 
     result = {
         "metric": METRIC,
@@ -349,6 +385,7 @@ def main():
         "plain_fp64": {"value": round(plain_gops, 3), "unit": "Gop/s", "ms": round(plain_ms, 4),
                        "frac_fp64_peak": round(plain_gops / 1e3 / PEAK_FP64_TFLOPS, 4)},
         "split_vs_plain": round(value / plain_gops, 4),
+        "split_int8": split_int8,
         "rel_diff_split_vs_plain": diff,
         "roofline": {"bound": "mfma", "kernel": "k_split_gemm<%d>" % S, "achieved": round(achieved, 2),
                      "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),

@@ -126,19 +126,22 @@ moa_status moa_outer(moa_shape sa, const void *A, moa_shape sb, const void *B, m
  * Each row of A and each column of B is scaled by a power of two so its
  * entries lie in (-1, 1), then written as `nslices` signed digits of beta
  * bits, each digit an integer the slice format holds exactly
- * (MOA_SPLIT_BF16: beta = 9, |digit| <= 256; MOA_SPLIT_FP8: FP8 E4M3 digits,
- * beta = 5, |digit| <= 16). The slice pairs (s, t) with s + t < nslices are
- * multiplied on the matrix cores with FP32 accumulation that is exact for the
- * leading weights, summed in FP64 and scaled back exactly.
+ * (MOA_SPLIT_BF16: beta = 9, |digit| <= 256, FP32 accumulation, exact for the
+ * leading weights; MOA_SPLIT_INT8: beta = 7, |digit| <= 64, INT32
+ * accumulation, exact; MOA_SPLIT_FP8 is reserved and not built). The slice
+ * pairs (s, t) with s + t < nslices are multiplied on the matrix cores,
+ * summed in FP64 and scaled back exactly.
  * Requirements: finite inputs; 1 <= nslices <= MOA_SPLIT_MAX_SLICES.
- * Accuracy (BF16, nslices = 5, entries u*2^k with k in [-8, 8], K = 8192):
- * normwise relative error about 7e-13 against an exactly rounded product.
+ * Accuracy (entries u*2^k with k in [-8, 8], K = 8192), normwise relative
+ * error against an exactly rounded product: BF16, nslices = 5 (15 pairs):
+ * about 7e-13; INT8, nslices = 7 (28 pairs): about 5e-14.
  *
  * ws: device workspace of at least moa_inner_split_workspace(...) bytes, owned
  * by the caller, 256-byte aligned; contents on entry are ignored.
  */
 #define MOA_SPLIT_BF16 0
 #define MOA_SPLIT_FP8 1
+#define MOA_SPLIT_INT8 2
 #define MOA_SPLIT_MAX_SLICES 7
 size_t moa_inner_split_workspace(moa_shape sa, moa_shape sb, int32_t fmt, int32_t nslices);
 moa_status moa_inner_split(moa_shape sa, const double *A, moa_shape sb, const double *B, double *D, int32_t fmt,

@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(_HERE, "libmoa.so")
 
 OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "max": 4, "min": 5, "and": 6, "or": 7, "xor": 8}
 DTYPES = {torch.float64: 0, torch.float32: 1, torch.int32: 2}
-SPLIT_FORMATS = {"bf16": 0, "fp8": 1}
+SPLIT_FORMATS = {"bf16": 0, "fp8": 1, "int8": 2}
 FLAG_SEQUENTIAL_FOLD = 1
 MAX_RANK = 16
 

@@ -145,6 +145,110 @@ __global__ __launch_bounds__(256) void k_slice_b(const double *__restrict__ B, i
   for (int s = 0; s < S; ++s) dst[s * 64] = sig[s];
 }
 
+// INT8 slices (MOA_SPLIT_INT8): signed digits of 7 bits, |digit| <= 64,
+// chunk = 64 lanes x 16 INT8 (a 32 x 32 operand of v_mfma_i32_32x32x32_i8,
+// lane l holding row/col l % 32 and k = 16 * (l / 32) .. + 15).
+template <int S>
+__device__ __forceinline__ void digits16_i8(const double v[16], int e, split::i8::intx4 sig[S]) {
+  constexpr int kB = split::i8::kBeta;
+#pragma unroll
+  for (int s = 0; s < S; ++s) sig[s] = split::i8::intx4{0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    double r = ldexp(v[q], kB - 1 - e);  // x * 2^(beta-1), exact
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double d = rint(r);
+      sig[s][q / 4] |= ((int)d & 0xff) << (8 * (q % 4));
+      r = (r - d) * (double)(1 << kB);
+    }
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_slice_a_i8(const double *__restrict__ A, int64_t M, int64_t K,
+                                                    const uint64_t *__restrict__ rowmax, int64_t KB, int64_t nchunks,
+                                                    split::i8::intx4 *__restrict__ Apk) {
+  const int64_t blk = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (blk >= nchunks) return;
+  const int lane = threadIdx.x % 64;
+  const int64_t mb = blk / KB, kb = blk % KB;
+  const int64_t row = mb * 32 + lane % 32;
+  const int64_t k0 = kb * 32 + (lane / 32) * 16;
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = (row < M && k0 + q < K) ? A[row * K + k0 + q] : 0.0;
+  const int e = exponent_of_max(rowmax[row]);
+  split::i8::intx4 sig[S];
+  digits16_i8<S>(v, e, sig);
+  split::i8::intx4 *dst = Apk + (blk * S) * 64 + lane;
+#pragma unroll
+  for (int s = 0; s < S; ++s) dst[s * 64] = sig[s];
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_slice_b_i8(const double *__restrict__ B, int64_t K, int64_t N,
+                                                    const uint64_t *__restrict__ colmax, int64_t KB, int64_t nchunks,
+                                                    split::i8::intx4 *__restrict__ Bpk) {
+  const int64_t blk = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (blk >= nchunks) return;
+  const int lane = threadIdx.x % 64;
+  const int64_t nb = blk / KB, kb = blk % KB;
+  const int64_t col = nb * 32 + lane % 32;
+  const int64_t k0 = kb * 32 + (lane / 32) * 16;
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = (col < N && k0 + q < K) ? B[(k0 + q) * N + col] : 0.0;
+  const int e = (col < N) ? exponent_of_max(colmax[col]) : 0;
+  split::i8::intx4 sig[S];
+  digits16_i8<S>(v, e, sig);
+  split::i8::intx4 *dst = Bpk + (blk * S) * 64 + lane;
+#pragma unroll
+  for (int s = 0; s < S; ++s) dst[s * 64] = sig[s];
+}
+
+// Scans shared by both formats.
+static void launch_scans(const SplitPlan &p, const double *A, const double *B, uint64_t *rowmax, uint64_t *colmax,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)((p.Mp + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, p.Mp);
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((p.Np + 255) / 256)), dim3(256), 0, s, colmax, p.Np);
+  const int64_t band = 128;
+  dim3 gcols((unsigned)((p.N + 255) / 256), (unsigned)((p.K + band - 1) / band));
+  if (p.N > 0 && p.K > 0) hipLaunchKernelGGL(k_scan_cols, gcols, dim3(256), 0, s, B, p.K, p.N, band, colmax);
+}
+
+template <int S>
+hipError_t launch_prepare_i8(const SplitPlan &p, const double *A, const double *B, void *ws, hipStream_t s) {
+  char *w = (char *)ws;
+  uint64_t *rowmax = (uint64_t *)(w + p.off_ea);
+  uint64_t *colmax = (uint64_t *)(w + p.off_fb);
+  auto *Apk = (split::i8::intx4 *)(w + p.off_ap);
+  auto *Bpk = (split::i8::intx4 *)(w + p.off_bp);
+  const int64_t KB = p.Kp / 32;
+  launch_scans(p, A, B, rowmax, colmax, s);
+  const int64_t cha = (p.Mp / 32) * KB, chb = (p.Np / 32) * KB;
+  hipLaunchKernelGGL((k_slice_a_i8<S>), dim3((unsigned)((cha + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, KB,
+                     cha, Apk);
+  hipLaunchKernelGGL((k_slice_b_i8<S>), dim3((unsigned)((chb + 3) / 4)), dim3(256), 0, s, B, p.K, p.N, colmax, KB,
+                     chb, Bpk);
+  return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_multiply_i8(const SplitPlan &p, double *D, void *ws, hipStream_t s) {
+  char *w = (char *)ws;
+  const uint64_t *rowmax = (const uint64_t *)(w + p.off_ea);
+  const uint64_t *colmax = (const uint64_t *)(w + p.off_fb);
+  const auto *Apk = (const split::i8::intx4 *)(w + p.off_ap);
+  const auto *Bpk = (const split::i8::intx4 *)(w + p.off_bp);
+  const int64_t KB = p.Kp / 32;
+  using C = split::i8::Cfg<S, 2, 4>;
+  const int64_t tmn = p.Mp / C::BM, tnn = p.Np / C::BN;
+  hipLaunchKernelGGL((split::i8::k_split_gemm_i8<S, 2, 4>), dim3((unsigned)(tmn * tnn)), dim3(C::kThreads), 0, s,
+                     Apk, Bpk, rowmax, colmax, D, p.M, p.N, KB, tmn, tnn);
+  return hipGetLastError();
+}
+
 template <int S>
 hipError_t launch_prepare_s(const SplitPlan &p, const double *A, const double *B, void *ws, hipStream_t s) {
   char *w = (char *)ws;
@@ -153,11 +257,7 @@ hipError_t launch_prepare_s(const SplitPlan &p, const double *A, const double *B
   bf16x8 *Apk = (bf16x8 *)(w + p.off_ap);
   bf16x8 *Bpk = (bf16x8 *)(w + p.off_bp);
   const int64_t KB = p.Kp / 16;
-  hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)((p.Mp + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, p.Mp);
-  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((p.Np + 255) / 256)), dim3(256), 0, s, colmax, p.Np);
-  const int64_t band = 128;
-  dim3 gcols((unsigned)((p.N + 255) / 256), (unsigned)((p.K + band - 1) / band));
-  if (p.N > 0 && p.K > 0) hipLaunchKernelGGL(k_scan_cols, gcols, dim3(256), 0, s, B, p.K, p.N, band, colmax);
+  launch_scans(p, A, B, rowmax, colmax, s);
   const int64_t cha = (p.Mp / 32) * KB, chb = (p.Np / 32) * KB;
   hipLaunchKernelGGL((k_slice_a<S>), dim3((unsigned)((cha + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, KB, cha,
                      Apk);
@@ -187,32 +287,53 @@ static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool split_plan(int64_t M, int64_t K, int64_t N, int fmt, int S, SplitPlan *p) {
-  if (fmt != MOA_SPLIT_BF16 || S < 1 || S > MOA_SPLIT_MAX_SLICES) return false;
+  if ((fmt != MOA_SPLIT_BF16 && fmt != MOA_SPLIT_INT8) || S < 1 || S > MOA_SPLIT_MAX_SLICES) return false;
   p->M = M;
   p->K = K;
   p->N = N;
   p->fmt = fmt;
   p->S = S;
-  p->beta = kBeta;
-  int bm, bn;
-  tile_of(S, &bm, &bn);
+  int bm, bn, bytes;
+  if (fmt == MOA_SPLIT_BF16) {
+    p->beta = kBeta;
+    tile_of(S, &bm, &bn);
+    p->Kp = round_up(K > 0 ? K : 1, kFlushK);
+    bytes = 2;
+  } else {
+    p->beta = split::i8::kBeta;
+    bm = split::i8::Cfg<1, 2, 4>::BM;
+    bn = split::i8::Cfg<1, 2, 4>::BN;
+    p->Kp = round_up(K > 0 ? K : 1, 32);
+    bytes = 1;
+  }
   p->Mp = round_up(M > 0 ? M : 1, bm);
   p->Np = round_up(N > 0 ? N : 1, bn);
-  p->Kp = round_up(K > 0 ? K : 1, kFlushK);
   size_t off = 0;
   p->off_ea = off;
   off = align256(off + sizeof(uint64_t) * (size_t)p->Mp);
   p->off_fb = off;
   off = align256(off + sizeof(uint64_t) * (size_t)p->Np);
   p->off_ap = off;
-  off = align256(off + 2 * (size_t)S * (size_t)p->Mp * (size_t)p->Kp);
+  off = align256(off + (size_t)bytes * (size_t)S * (size_t)p->Mp * (size_t)p->Kp);
   p->off_bp = off;
-  off = align256(off + 2 * (size_t)S * (size_t)p->Np * (size_t)p->Kp);
+  off = align256(off + (size_t)bytes * (size_t)S * (size_t)p->Np * (size_t)p->Kp);
   p->total = off;
   return true;
 }
 
 hipError_t launch_split_prepare(const SplitPlan &p, const double *A, const double *B, void *ws, hipStream_t s) {
+  if (p.fmt == MOA_SPLIT_INT8) {
+    switch (p.S) {
+      case 1: return launch_prepare_i8<1>(p, A, B, ws, s);
+      case 2: return launch_prepare_i8<2>(p, A, B, ws, s);
+      case 3: return launch_prepare_i8<3>(p, A, B, ws, s);
+      case 4: return launch_prepare_i8<4>(p, A, B, ws, s);
+      case 5: return launch_prepare_i8<5>(p, A, B, ws, s);
+      case 6: return launch_prepare_i8<6>(p, A, B, ws, s);
+      case 7: return launch_prepare_i8<7>(p, A, B, ws, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (p.S) {
     case 1: return launch_prepare_s<1>(p, A, B, ws, s);
     case 2: return launch_prepare_s<2>(p, A, B, ws, s);
@@ -226,6 +347,18 @@ hipError_t launch_split_prepare(const SplitPlan &p, const double *A, const doubl
 }
 
 hipError_t launch_split_multiply(const SplitPlan &p, double *D, void *ws, hipStream_t s) {
+  if (p.fmt == MOA_SPLIT_INT8) {
+    switch (p.S) {
+      case 1: return launch_multiply_i8<1>(p, D, ws, s);
+      case 2: return launch_multiply_i8<2>(p, D, ws, s);
+      case 3: return launch_multiply_i8<3>(p, D, ws, s);
+      case 4: return launch_multiply_i8<4>(p, D, ws, s);
+      case 5: return launch_multiply_i8<5>(p, D, ws, s);
+      case 6: return launch_multiply_i8<6>(p, D, ws, s);
+      case 7: return launch_multiply_i8<7>(p, D, ws, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (p.S) {
     case 1: return launch_multiply_s<1>(p, D, ws, s);
     case 2: return launch_multiply_s<2>(p, D, ws, s);

@@ -244,7 +244,8 @@ namespace {
 // caller does not pass them (checked by the caller).
 moa_status split_check(moa_shape sa, moa_shape sb, int32_t fmt, int32_t nslices, void *ws, size_t ws_bytes, Flat *f,
                        moa::SplitPlan *p) {
-  if (fmt != MOA_SPLIT_BF16 && fmt != MOA_SPLIT_FP8) return fail(MOA_ERR_ARG, "unknown split format %d", fmt);
+  if (fmt != MOA_SPLIT_BF16 && fmt != MOA_SPLIT_FP8 && fmt != MOA_SPLIT_INT8)
+    return fail(MOA_ERR_ARG, "unknown split format %d", fmt);
   if (fmt == MOA_SPLIT_FP8) return fail(MOA_ERR_ARG, "FP8 slices are not built in this library");
   if (nslices < 1 || nslices > MOA_SPLIT_MAX_SLICES)
     return fail(MOA_ERR_ARG, "nslices %d outside [1, %d]", nslices, MOA_SPLIT_MAX_SLICES);

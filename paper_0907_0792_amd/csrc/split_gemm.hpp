@@ -241,5 +241,134 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
 }
 
 
+
+// ---------------------------------------------------------------------------
+// INT8 slices: signed digits of 7 bits (|digit| <= 64), so a digit product is
+// at most 2^12 and v_mfma_i32_32x32x32_i8 accumulates every level exactly in
+// INT32 for 8192 k (level d has d+1 <= 7 pairs: 7 * 8192 * 2^12 < 2^31). A
+// level is folded into FP64 (times 2^-7d) only every 8192 k and at the end.
+// Chunk = 64 lanes x 16 INT8 = one 32x32 operand (lane l: row/col l % 32,
+// k = 16 * (l / 32) .. + 15); chunks ordered [row block][k block (32)][slice].
+// LDS holds three 32-k stages in rotation (two in flight), one barrier per
+// stage.
+namespace i8 {
+
+constexpr int kBeta = 7;
+constexpr int kNBuf = 3;
+constexpr int kFoldStages = 256;  // 8192 k
+
+typedef __attribute__((__vector_size__(4 * sizeof(int)))) int intx4;
+typedef __attribute__((__vector_size__(16 * sizeof(int)))) int intx16;
+
+template <int S, int WMW, int WNW>
+struct Cfg {
+  static constexpr int kWaves = WMW * WNW;
+  static constexpr int kThreads = 64 * kWaves;
+  static constexpr int BM = 32 * WMW, BN = 32 * WNW;
+  static constexpr int MBW = WMW, NBW = WNW;
+  static constexpr int A_CH = MBW * S, B_CH = NBW * S, ST_CH = A_CH + B_CH;
+  static constexpr int PER_WAVE = ST_CH / kWaves;
+  static constexpr int MAX_WAVE = (ST_CH + kWaves - 1) / kWaves;
+  static constexpr int EXTRA = ST_CH % kWaves;
+};
+
+template <int S, int WMW, int WNW>
+__global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_i8(
+    const intx4 *__restrict__ Apk, const intx4 *__restrict__ Bpk, const uint64_t *__restrict__ rowmax,
+    const uint64_t *__restrict__ colmax, double *__restrict__ D, int64_t M, int64_t N, int64_t KB, int64_t tiles_m,
+    int64_t tiles_n) {
+  using C = Cfg<S, WMW, WNW>;
+  __shared__ intx4 lds[kNBuf][C::ST_CH * 64];
+
+  int64_t tm, tn;
+  grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
+  const int tid = threadIdx.x, lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int wm = wave / WNW, wn = wave % WNW;
+
+  auto issue_stage = [&](int64_t st, int buf) {
+#pragma unroll
+    for (int q = 0; q < C::MAX_WAVE; ++q) {
+      const int c = wave + C::kWaves * q;
+      if (c >= C::ST_CH) break;
+      const intx4 *src;
+      if (c < C::A_CH) {
+        const int mbl = c / S, s = c % S;
+        src = Apk + (((tm * C::MBW + mbl) * KB + st) * S + s) * 64;
+      } else {
+        const int cb = c - C::A_CH;
+        const int nbl = cb / S, t = cb % S;
+        src = Bpk + (((tn * C::NBW + nbl) * KB + st) * S + t) * 64;
+      }
+      __builtin_amdgcn_global_load_lds((const void *)(src + lane),
+                                       (__attribute__((address_space(3))) void *)&lds[buf][c * 64], 16, 0, 0);
+    }
+  };
+
+  intx16 acc[S];
+  double acc64[16];
+  const intx16 zero16 = {};
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc64[v] = 0.0;
+#pragma unroll
+  for (int d = 0; d < S; ++d) acc[d] = zero16;
+
+  auto fold_all = [&]() {
+#pragma unroll
+    for (int d = S - 1; d >= 0; --d) {
+      const double w = __builtin_ldexp(1.0, -kBeta * d);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc64[v] = fma((double)acc[d][v], w, acc64[v]);
+      acc[d] = zero16;
+    }
+  };
+
+  const int64_t nst = KB;
+  issue_stage(0, 0);
+  if (1 < nst) issue_stage(1, 1);
+  for (int64_t st = 0; st < nst; ++st) {
+    const int buf = (int)(st % kNBuf);
+    // The copies of stage st + 1 may stay in flight.
+    if (st + 1 < nst) {
+      if (wave < C::EXTRA)
+        __builtin_amdgcn_s_waitcnt(0x0F70 | C::MAX_WAVE);
+      else
+        __builtin_amdgcn_s_waitcnt(0x0F70 | C::PER_WAVE);
+    } else {
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+    }
+    // Plain barrier (no fence): this stage is visible, and the buffer of
+    // stage st - 1 is free for stage st + 2.
+    __builtin_amdgcn_s_barrier();
+    if (st + 2 < nst) issue_stage(st + 2, (int)((st + 2) % kNBuf));
+    intx4 af[S], bfr[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) af[s] = lds[buf][(wm * S + s) * 64 + lane];
+#pragma unroll
+    for (int t = 0; t < S; ++t) bfr[t] = lds[buf][C::A_CH * 64 + (wn * S + t) * 64 + lane];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < S; ++r)
+#pragma unroll
+      for (int d = S - 1; d >= r; --d) acc[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bfr[d - r], acc[d], 0, 0, 0);
+    if ((st + 1) % kFoldStages == 0) fold_all();
+  }
+  if (nst % kFoldStages != 0) fold_all();
+
+  // D[i, j] = 2^(e_i + f_j - 2(beta-1)) * acc.
+  const int64_t gn = tn * C::BN + wn * 32 + lane % 32;
+  const int fe = (gn < N) ? exponent_of_max(colmax[gn]) : 0;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int64_t gm = tm * C::BM + wm * 32 + (v / 4) * 8 + (lane / 32) * 4 + (v % 4);
+    if (gm < M && gn < N) {
+      const int ee = exponent_of_max(rowmax[gm]);
+      D[gm * N + gn] = ldexp(acc64[v], ee + fe - 2 * (kBeta - 1));
+    }
+  }
+}
+
+}  // namespace i8
+
 }  // namespace split
 }  // namespace moa

@@ -125,6 +125,8 @@ def test_split_workspace_and_validation():
     assert n < 2 * 5 * 8192 * 8192 * 2 + 4 * 8192 * 8 + 4096
     assert moa.split_workspace_bytes((3, 5), (6, 2), "bf16", 5) == 0
     assert moa.split_workspace_bytes((3, 5), (5, 2), "bf16", 9) == 0
+    n8 = moa.split_workspace_bytes((8192, 8192), (8192, 8192), "int8", 7)
+    assert 2 * 7 * 8192 * 8192 <= n8 < 2 * 7 * 8192 * 8192 + 4 * 8192 * 8 + 4096
     sh = moa._shape
     z = ctypes.c_void_p
     args = (sh((4, 8)), z(0x100000), sh((8, 2)), z(0x200000), z(0x300000))

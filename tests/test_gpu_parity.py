@@ -281,6 +281,48 @@ def test_split_full_size_sampled():
     assert nerr(got[:6], want) <= 1e-14
 
 
+@pytest.mark.parametrize("shape", [(100, 300, 70), (64, 32, 128), (1, 1, 1), (257, 1000, 131), (33, 65, 200)])
+def test_split_int8_matches_oracle_scheme(shape):
+    M, K, N = shape
+    rng = np.random.default_rng(107)
+    a = mi.scaled_f64(rng, (M, K))
+    b = mi.scaled_f64(rng, (K, N))
+    ref = oracle.inner_dot2(a, b)
+    for S in range(1, 8):
+        say("split int8", shape, "S", S)
+        d = host(moa.inner_split(gpu(a), gpu(b), "int8", S))
+        want = oracle.split_inner(a, b, nslices=S, beta=7)
+        assert nerr(d, want) <= 1e-14, (S, nerr(d, want))
+        if S == 7:
+            assert nerr(d, ref) <= 1e-12, (S, nerr(d, ref))
+
+
+def test_split_int8_exact_integers():
+    # Integers in [-63, 63] whose row/column maximum lies in [32, 64) are one
+    # signed 7-bit digit each: one INT8 slice gives the exact product.
+    rng = np.random.default_rng(108)
+    a = mi.small_int_f64(rng, (90, 700), 63)
+    b = mi.small_int_f64(rng, (700, 70), 63)
+    a[:, 3] = 40.0
+    b[5, :] = -50.0
+    say("split int8 exact integers")
+    d = host(moa.inner_split(gpu(a), gpu(b), "int8", 1))
+    eq(d, (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
+
+
+def test_split_int8_full_size_sampled():
+    a, b = mi.workload_split()
+    say("split int8 8192^3 S=7")
+    d = moa.inner_split(gpu(a), gpu(b), "int8", 7)
+    rows = _sample_rows(np.random.default_rng(9), 8192, 10)
+    got = host(d[torch.from_numpy(rows).to(DEV)])
+    e = nerr(got, oracle.inner_dot2(a, b, rows=rows))
+    say("split int8 8192^3 err vs Dot2 %.3e" % e)
+    assert e <= 1e-12
+    want = oracle.split_inner(a, b, nslices=7, beta=7, rows=rows[:4])
+    assert nerr(got[:4], want) <= 1e-14
+
+
 # ---------------------------------------------------------------------------
 # Differentiation.
 

@@ -331,7 +331,7 @@ def test_dot2_ill_conditioned_exact():
 # --------------------------------------------------------------------------
 # Split scheme (Ozaki et al. 2012), signed digits.
 
-@pytest.mark.parametrize("fmt,beta", [("bf16", 8), ("bf16", 9), ("fp8", 5)])
+@pytest.mark.parametrize("fmt,beta", [("bf16", 8), ("bf16", 9), ("fp8", 5), ("bf16", 7)])
 def test_split_digits_bounds_and_exact_reconstruction(fmt, beta):
     rng = np.random.default_rng(24)
     x = mi.scaled_f64(rng, (20, 33))
@@ -361,6 +361,9 @@ def test_split_digit_representable_in_format():
     _, sig8 = oracle.split_digits(x, fmt="fp8", nslices=8)
     t8 = torch.from_numpy(sig8.astype(np.float32))
     assert torch.equal(t8.to(torch.float8_e4m3fn).to(torch.float32), t8)
+    # 7-bit signed digits fit INT8.
+    _, sig7 = oracle.split_digits(x, nslices=7, beta=7)
+    assert np.array_equal(sig7.astype(np.int8).astype(np.int32), sig7)
 
 
 def test_split_exact_for_small_integers():
@@ -421,6 +424,18 @@ def test_split_power_of_two_scaling_invariance():
     want[2] = np.ldexp(want[2], -7)
     want[:, 1] = np.ldexp(want[:, 1], 3)
     assert np.array_equal(d2, want)
+
+
+def test_split_int8_parameters_meet_tolerance_on_workload_distribution():
+    # INT8 digits of 7 bits, 7 slices (28 pairs), same distribution.
+    rng = mi.rng_for(mi.SPLIT_PRECISION, salt=4)
+    a = mi.scaled_f64(rng, (8, 8192))
+    b = mi.scaled_f64(rng, (8192, 32))
+    ref = oracle.inner_dot2(a, b)
+    err = oracle.normwise_error(oracle.split_inner(a, b, nslices=7, beta=7), ref)
+    assert err <= 1e-12, err
+    # Six slices are not enough at this distribution.
+    assert oracle.normwise_error(oracle.split_inner(a, b, nslices=6, beta=7), ref) > 1e-12
 
 
 def test_split_chosen_parameters_meet_tolerance_on_workload_distribution():
