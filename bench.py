@@ -21,7 +21,8 @@ same fields, their own roofline): plain64 (FP64 (+,*) 8192^3), rank5 (FP64
 (+,*) <64 64 32 256>.<256 128 64>), tropical (int32 (max,+) 2048^3), outer
 (FP32 (-) <512 512> o <64 64>), batch (10,000 uneven FP32 products, one graph
 launch), grad (FP32 forward + backward <32 128 512>.<512 64 64>), small
-(FP64 512^3 plus the <32 32> o <16 16> outer product).
+(FP64 512^3 plus the <32 32> o <16 16> outer product), skinny (the paper's
+own FP64 4 x 128 . 128 x 2^22 product, HBM-bound).
 """
 from __future__ import annotations
 
@@ -156,6 +157,22 @@ def other_workload(args):
                     roofline={"bound": "mfma", "kernel": "k_gemm<double>", "achieved": round(t, 3),
                               "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(t / PEAK_FP64_TFLOPS, 4),
                               "traffic": None})
+    if w == "skinny":
+        a_h, b_h = mi.workload_skinny()
+        a, b = put(a_h), put(b_h)
+        m, k, n = a_h.shape[0], a_h.shape[1], b_h.shape[1]
+        out = torch.empty((m, n), dtype=torch.float64, device=dev)
+        ms, wall = _time_events(lambda: moa.inner(a, b, out=out), args.steps, args.warmup)
+        nbytes = 8.0 * (k * n + m * n + m * k)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return dict(base, metric="few-row inner product GB/s", value=round(gbs, 2), unit="GB/s",
+                    ms_per_step=round(ms, 4), dtype="f64",
+                    gops=round(2.0 * m * k * n / (ms * 1e-3) / 1e9, 2),
+                    config={"workload": "FP64 (+,*) %d x %d . %d x %d (the paper's m x 128 . 128 x n matrix product)"
+                                        % (m, k, k, n), "m": m, "k": k, "n": n},
+                    roofline={"bound": "hbm", "kernel": "k_skinny<double,add,mul,%d>" % m, "achieved": round(gbs, 2),
+                              "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                              "traffic": None})
     if w == "tropical":
         a_h, b_h = mi.workload_tropical()
         a, b = put(a_h), put(b_h)
@@ -235,7 +252,7 @@ def main():
     ap.add_argument("--plain-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="split",
-                    choices=["split", "plain64", "rank5", "tropical", "outer", "batch", "grad", "small"])
+                    choices=["split", "plain64", "rank5", "tropical", "outer", "batch", "grad", "small", "skinny"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()

@@ -33,7 +33,9 @@
  * FP (op1, op2) pairs other than (+,*) fold in ascending p, one IEEE
  * operation per step, so they match a sequential fold bit for bit. (+,*) on
  * FP64 / FP32 runs on the matrix cores in another summation order (normwise
- * relative error of order K * unit roundoff).
+ * relative error of order K * unit roundoff), except for results with at most
+ * 8 rows (product of rhoA[:-1]) and at least 4096 columns, which stream B
+ * once and fold in ascending p like every other pair.
  *
  * Errors. Every call validates on the host before any launch and returns a
  * moa_status; nothing is launched on an error. Kernel execution is

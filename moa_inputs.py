@@ -173,6 +173,12 @@ def workload_split(rng=None, m=8192, k=8192, n=8192):
     return scaled_f64(rng, (m, k)), scaled_f64(rng, (k, n))
 
 
+def workload_skinny(rng=None, m=4, k=128, n=1 << 22):
+    """Section II.B's matrix product: A is m x 128 (m = 1..4), B is 128 x n."""
+    rng = rng or rng_for(RANK_GENERAL, salt=5)
+    return uniform_f64(rng, (m, k)), uniform_f64(rng, (k, n))
+
+
 def workload_grad(rng=None, sa=(32, 128, 512), sb=(512, 64, 64)):
     rng = rng or rng_for(DIFFERENTIATION)
     a = uniform_f32(rng, sa)

@@ -16,6 +16,12 @@ namespace moa {
 hipError_t launch_simt_inner(moa_dtype dt, moa_op op1, moa_op op2, const void *A, const void *B, void *D, int64_t M,
                              int64_t K, int64_t N, int tile, hipStream_t s);
 
+// Few-row inner product (M <= kSkinnyMaxRows): the row form as an HBM stream,
+// every element of B read once, ascending-l fold (bit-exact, any op pair).
+constexpr int64_t kSkinnyMaxRows = 8;
+hipError_t launch_skinny_inner(moa_dtype dt, moa_op op1, moa_op op2, const void *A, const void *B, void *D, int64_t M,
+                               int64_t K, int64_t N, hipStream_t s);
+
 // C (NA x NB) = op(A[i], B[j]).
 hipError_t launch_outer(moa_dtype dt, moa_op op, const void *A, const void *B, void *C, int64_t NA, int64_t NB,
                         hipStream_t s);

@@ -206,6 +206,9 @@ moa_status moa_inner_ex(moa_shape sa, const void *A, moa_shape sb, const void *B
   if (f.nD == 0) return MOA_OK;
   hipStream_t s = (hipStream_t)stream;
   if (f.K == 0) return hip_status(moa::launch_fill_identity(dt, op1, D, f.nD, s), "identity fill");
+  // Few result rows and long rows of B: the row-form stream reads B once.
+  if (f.M <= moa::kSkinnyMaxRows && f.N >= 4096)
+    return hip_status(moa::launch_skinny_inner(dt, op1, op2, A, B, D, f.M, f.K, f.N, s), "inner (few rows)");
   const bool mfma = op1 == MOA_ADD && op2 == MOA_MUL && dt != MOA_I32 && !(flags & MOA_FLAG_SEQUENTIAL_FOLD);
   if (mfma) return hip_status(moa::launch_gemm(dt, false, false, A, B, D, f.M, f.K, f.N, 0, s), "inner (+,*)");
   return hip_status(moa::launch_simt_inner(dt, op1, op2, A, B, D, f.M, f.K, f.N, 0, s), "inner");

@@ -121,6 +121,32 @@ def test_simt_tiles_and_tails(tile):
     eq(host(moa.inner(gpu(af), gpu(bf), "add", "sub")), oracle.inner(af, bf, "add", "sub", mode="native"))
 
 
+@pytest.mark.parametrize("dt", [np.float64, np.float32, np.int32])
+def test_few_rows_stream_all_pairs_bit_exact(dt):
+    # At most 8 result rows and >= 4096 columns: the row-form stream kernel,
+    # ascending fold for every pair, (+,*) included.
+    rng = np.random.default_rng(109)
+    folds = FOLD_I if dt == np.int32 else FOLD_F
+    elems = ELEM_I if dt == np.int32 else ELEM_F
+    for M, K, N in [(1, 128, 4096), (3, 37, 5003), (8, 5, 4100), (2, 1, 8192)]:
+        a = rand(rng, (M, K), dt)
+        b = rand(rng, (K, N), dt)
+        ga, gb = gpu(a), gpu(b)
+        for op1 in folds:
+            for op2 in elems:
+                say("few rows", np.dtype(dt).name, M, K, N, op1, op2)
+                eq(host(moa.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
+
+
+def test_few_rows_paper_workload_full():
+    # Section II.B: A m x 128 (m = 4), B 128 x n, n = 2^22; every row checked.
+    a, b = mi.workload_skinny()
+    say("few rows 4 x 128 . 128 x 2^22")
+    d = host(moa.inner(gpu(a), gpu(b)))
+    eq(d, oracle.inner(a, b))
+    assert nerr(d, oracle.inner_dot2(a, b)) <= 1e-14
+
+
 def test_empty_and_degenerate():
     for dt in (np.float64, np.int32):
         a = np.zeros((3, 0), dtype=dt)
