@@ -157,6 +157,27 @@ def other_workload(args):
                     roofline={"bound": "mfma", "kernel": "k_gemm<double>", "achieved": round(t, 3),
                               "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(t / PEAK_FP64_TFLOPS, 4),
                               "traffic": None})
+    if w == "axes":
+        a_h, b_h = mi.workload_axes()
+        a, b = put(a_h), put(b_h)
+        M = a_h.shape[0] * a_h.shape[2]
+        K = a_h.shape[1]
+        N = b_h.shape[0] * b_h.shape[2]
+        out = torch.empty(moa.inner_axes_shape(a.shape, 1, b.shape, 1), dtype=torch.float64, device=dev)
+        ms, wall = _time_events(lambda: moa.inner_axes(a, b, (1, 1), out=out), args.steps, args.warmup)
+        # Same M x K . K x N with plain layouts, for the cost of the strided views.
+        ap, bp = a.reshape(M, K), b.reshape(K, N)
+        outp = torch.empty((M, N), dtype=torch.float64, device=dev)
+        ms_plain, _ = _time_events(lambda: moa.inner(ap, bp, out=outp), args.steps, args.warmup)
+        flops = 2.0 * M * N * K
+        t = flops / (ms * 1e-3) / 1e12
+        return dict(base, metric="inner-product Gop/s (any-axis contraction)", value=round(flops / (ms * 1e-3) / 1e9, 3),
+                    unit="Gop/s", ms_per_step=round(ms, 4), dtype="f64", plain_layout_ms=round(ms_plain, 4),
+                    config={"workload": "FP64 (+,*) <16 2048 512> . <16 2048 512> over axes (1, 1) -> "
+                                        "<16 512 16 512>, U[-1,1]", "m": M, "k": K, "n": N},
+                    roofline={"bound": "mfma", "kernel": "k_gemm<double, TA=1, TB=0, 4x4, GEN=1>", "achieved": round(t, 3),
+                              "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(t / PEAK_FP64_TFLOPS, 4),
+                              "traffic": None})
     if w == "skinny":
         a_h, b_h = mi.workload_skinny()
         a, b = put(a_h), put(b_h)
@@ -252,7 +273,8 @@ def main():
     ap.add_argument("--plain-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="split",
-                    choices=["split", "plain64", "rank5", "tropical", "outer", "batch", "grad", "small", "skinny"])
+                    choices=["split", "plain64", "rank5", "tropical", "outer", "batch", "grad", "small", "skinny",
+                             "axes"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()

@@ -113,6 +113,27 @@ moa_status moa_inner_ex(moa_shape sa, const void *A, moa_shape sb, const void *B
                         moa_dtype dt, void *D, uint32_t flags, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Generalized inner product over any axis pair: the contraction of Eq. inner
+ * (Section I, where the inner product is shown to be a tensor contraction)
+ * taken over axis ax_a of A and axis ax_b of B instead of the last and the
+ * first. Both operands are read in place through start/stride/count index
+ * maps, the Operational Normal Form of Section II.D, with no transposed copy:
+ * A as (Pa, K, Qa) with Pa = prod rhoA[0:ax_a], K = rhoA[ax_a],
+ * Qa = prod rhoA[ax_a+1:], B likewise as (Pb, K, Qb), and
+ *   D[(pa, qa), (pb, qb)] = op1-fold_k op2(A[pa, k, qa], B[pb, k, qb]).
+ * The result shape is rhoA without axis ax_a ++ rhoB without axis ax_b (the
+ * axis order of numpy.tensordot(A, B, axes=(ax_a, ax_b))), row-major.
+ * ax_a = rank(A) - 1, ax_b = 0 is moa_inner_ex exactly. Requirements:
+ * 0 <= ax_a < rank(A), 0 <= ax_b < rank(B) (else MOA_ERR_ARG),
+ * rhoA[ax_a] = rhoB[ax_b] (else MOA_ERR_SHAPE); ops, dtypes, flags, aliasing
+ * and the fold order as for moa_inner_ex.
+ */
+moa_status moa_inner_axes_shape(moa_shape a, int32_t ax_a, moa_shape b, int32_t ax_b, int64_t *out_dims,
+                                int32_t *out_rank);
+moa_status moa_inner_axes(moa_shape sa, const void *A, int32_t ax_a, moa_shape sb, const void *B, int32_t ax_b,
+                          moa_op op1, moa_op op2, moa_dtype dt, void *D, uint32_t flags, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Generalized outer product (Section I, Eq. outer), computed by the same
  * definition as moa_inner with one contracted element. C has shape sa ++ sb.
  * Every element is one IEEE operation (bit-exact).

@@ -179,6 +179,13 @@ def workload_skinny(rng=None, m=4, k=128, n=1 << 22):
     return uniform_f64(rng, (m, k)), uniform_f64(rng, (k, n))
 
 
+def workload_axes(rng=None, sa=(16, 2048, 512), sb=(16, 2048, 512)):
+    """Contraction over a middle axis of both operands (axes (1, 1)):
+    8192 x 2048 . 2048 x 8192 read through strided views, U[-1, 1]."""
+    rng = rng or rng_for(RANK_GENERAL, salt=6)
+    return uniform_f64(rng, sa), uniform_f64(rng, sb)
+
+
 def workload_grad(rng=None, sa=(32, 128, 512), sb=(512, 64, 64)):
     rng = rng or rng_for(DIFFERENTIATION)
     a = uniform_f32(rng, sa)

@@ -120,6 +120,23 @@ def inner(a, b, op1="add", op2="mul", mode="wide", rows=None):
     return out.reshape(rs)
 
 
+def inner_axes(a, ax_a, b, ax_b, op1="add", op2="mul", mode="wide", rows=None):
+    """Eq. inner contracted over axis ax_a of A and axis ax_b of B (Section I:
+    the inner product as a tensor contraction over a chosen index pair).
+    Definition: move the contracted axis of A to the end and that of B to the
+    front (a transposition, no arithmetic), then the last-with-first product.
+    Result axes: A's free axes, then B's; ``rows`` indexes A's free part."""
+    a = np.asarray(a, order="C")
+    b = np.asarray(b, order="C")
+    if a.ndim < 1 or b.ndim < 1:
+        raise ValueError("inner product needs rank >= 1 operands")
+    ax_a = ax_a + a.ndim if ax_a < 0 else ax_a
+    ax_b = ax_b + b.ndim if ax_b < 0 else ax_b
+    if not (0 <= ax_a < a.ndim and 0 <= ax_b < b.ndim):
+        raise ValueError("axis out of range")
+    return inner(np.moveaxis(a, ax_a, -1), np.moveaxis(b, ax_b, 0), op1, op2, mode, rows)
+
+
 def outer(a, b, op="mul", mode="native"):
     """Generalized outer product C[i ++ j] = A[i] op B[j]. FP32 inputs give
     FP32 (each element one correctly rounded FP32 op) unless mode="wide"."""

@@ -119,3 +119,25 @@ def inner(a: np.ndarray, b: np.ndarray, op1: str, op2: str, identity=None) -> np
                     acc = t if acc is None else _apply(op1, acc, t, kind)
             out[tuple(i) + tuple(j)] = acc
     return out
+
+
+def inner_axes(a: np.ndarray, ax_a: int, b: np.ndarray, ax_b: int, op1: str, op2: str, identity=None) -> np.ndarray:
+    """Eq. inner contracted over axis ax_a of A and ax_b of B: every result
+    element is built from its free index tuples with p inserted at the
+    contracted positions."""
+    kind = _kind(a.dtype)
+    assert a.shape[ax_a] == b.shape[ax_b]
+    K = a.shape[ax_a]
+    fa = [n for d, n in enumerate(a.shape) if d != ax_a]
+    fb = [n for d, n in enumerate(b.shape) if d != ax_b]
+    out = np.empty(tuple(fa) + tuple(fb), dtype=a.dtype)
+    for i in itertools.product(*[range(n) for n in fa]):
+        for j in itertools.product(*[range(n) for n in fb]):
+            acc = identity
+            for p in range(K):
+                ia = tuple(i[:ax_a]) + (p,) + tuple(i[ax_a:])
+                jb = tuple(j[:ax_b]) + (p,) + tuple(j[ax_b:])
+                t = _apply(op2, _elem(a, ia), _elem(b, jb), kind)
+                acc = t if p == 0 else _apply(op1, acc, t, kind)
+            out[tuple(i) + tuple(j)] = acc
+    return out

@@ -70,6 +70,8 @@ def lib():
     L.moa_inner.argtypes = [S, vp, S, vp, i32, i32, i32, vp, vp]
     L.moa_inner_ex.argtypes = [S, vp, S, vp, i32, i32, i32, vp, u32, vp]
     L.moa_outer.argtypes = [S, vp, S, vp, i32, i32, vp, vp]
+    L.moa_inner_axes_shape.argtypes = [S, i32, S, i32, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.moa_inner_axes.argtypes = [S, vp, i32, S, vp, i32, i32, i32, i32, vp, u32, vp]
     L.moa_inner_split_workspace.restype = sz
     L.moa_inner_split_workspace.argtypes = [S, S, i32, i32]
     L.moa_inner_split.argtypes = [S, vp, S, vp, vp, i32, i32, vp, sz, vp]
@@ -86,6 +88,7 @@ def lib():
     L.moa_tile_table_get.argtypes = [ctypes.c_char_p, sz]
     L.moa_tile_table_set.argtypes = [ctypes.c_char_p]
     for name in ("moa_inner_shape", "moa_outer_shape", "moa_inner", "moa_inner_ex", "moa_outer", "moa_inner_split",
+                 "moa_inner_axes_shape", "moa_inner_axes",
                  "moa_inner_split_prepare", "moa_inner_split_multiply", "moa_inner_grad", "moa_batch_build", "moa_batch_run", "moa_batch_info", "moa_batch_autotune",
                  "moa_tile_table_get", "moa_tile_table_set"):
         getattr(L, name).restype = i32
@@ -131,6 +134,40 @@ def inner_shape(sa, sb):
     r = ctypes.c_int32()
     _check(lib().moa_inner_shape(_shape(sa), _shape(sb), out, ctypes.byref(r)))
     return tuple(out[i] for i in range(r.value))
+
+
+def _axis(ax, rank):
+    ax = int(ax)
+    return ax + rank if ax < 0 else ax
+
+
+def inner_axes_shape(sa, ax_a, sb, ax_b):
+    out = (ctypes.c_int64 * MAX_RANK)()
+    r = ctypes.c_int32()
+    _check(lib().moa_inner_axes_shape(_shape(sa), _axis(ax_a, len(sa)), _shape(sb), _axis(ax_b, len(sb)), out,
+                                      ctypes.byref(r)))
+    return tuple(out[i] for i in range(r.value))
+
+
+def inner_axes(a: torch.Tensor, b: torch.Tensor, axes=(-1, 0), op1: str = "add", op2: str = "mul", flags: int = 0,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    """Generalized inner product contracting axis axes[0] of A with axis axes[1]
+    of B, read in place (Section I, Eq. inner; index maps of Section II.D).
+    Axes may be negative. Result axes: A's free axes, then B's."""
+    if a.dtype != b.dtype or a.dtype not in DTYPES:
+        raise TypeError("operands must share dtype float64, float32 or int32")
+    dev = _dev_operands(a, b)
+    a = a.contiguous()
+    b = b.contiguous()
+    ax_a, ax_b = _axis(axes[0], a.dim()), _axis(axes[1], b.dim())
+    rs = inner_axes_shape(a.shape, ax_a, b.shape, ax_b)
+    if out is None:
+        out = torch.empty(rs, dtype=a.dtype, device=dev)
+    elif tuple(out.shape) != rs or out.dtype != a.dtype or not out.is_contiguous():
+        raise ValueError("out has the wrong shape, dtype or layout")
+    _check(lib().moa_inner_axes(_shape(a.shape), _ptr(a), ax_a, _shape(b.shape), _ptr(b), ax_b, OPS[op1], OPS[op2],
+                                DTYPES[a.dtype], _ptr(out), flags, _stream(dev)))
+    return out
 
 
 def outer_shape(sa, sb):

@@ -30,13 +30,19 @@ struct Mfma16<float> {
 };
 
 // One BM x BN tile of D = A . B (BM = 32*WBM, BN = 32*WBN), computed by the
-// 256 threads of a workgroup. m0, n0: tile origin.
-template <typename T, bool TA, bool TB, int WBM, int WBN>
+// 256 threads of a workgroup with BK-wide k panels. m0, n0: tile origin.
+// GEN: A and B are the strided (P, K, Q) views of a contraction over any
+// axis pair, A[i, k] = A[(i / Qa) K Qa + k Qa + i % Qa] and
+// B[k, j] = B[(j / Qb) K Qb + k Qb + j % Qb]; TA, TB then only choose which
+// index runs fastest across threads (TA: i, else k; TB: k, else j), so that
+// neighbouring lanes read neighbouring addresses.
+template <typename T, bool TA, bool TB, int WBM, int WBN, int BK = 16, bool GEN = false>
 __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
-                                          int64_t M, int64_t K, int64_t N, int64_t m0, int64_t n0) {
+                                          int64_t M, int64_t K, int64_t N, int64_t m0, int64_t n0, int64_t Qa = 1,
+                                          int64_t Qb = 1) {
   using MF = Mfma16<T>;
   using acc_t = typename MF::acc_t;
-  constexpr int BM = 32 * WBM, BN = 32 * WBN, BK = 16;
+  constexpr int BM = 32 * WBM, BN = 32 * WBN;
   constexpr int PAD = 2;
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
   __shared__ T As[BK][BM + PAD];
@@ -54,6 +60,23 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
       for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
 
   T ra[EA], rb[EB];
+  // GEN: the row/column part of each loaded element's address is the same for
+  // every k panel; -1 marks a row or column past the edge.
+  [[maybe_unused]] int64_t abase[GEN ? EA : 1], bbase[GEN ? EB : 1];
+  if constexpr (GEN) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int f = tid + 256 * e;
+      const int64_t gm = m0 + (TA ? f % BM : f / BK);
+      abase[e] = gm < M ? (gm / Qa) * K * Qa + gm % Qa : -1;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int f = tid + 256 * e;
+      const int64_t gn = n0 + (TB ? f / BK : f % BN);
+      bbase[e] = gn < N ? (gn / Qb) * K * Qb + gn % Qb : -1;
+    }
+  }
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
@@ -67,7 +90,10 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
         gm = m0 + f % BM;
       }
       const bool ok = gm < M && gk < K;
-      ra[e] = ok ? (TA ? A[gk * M + gm] : A[gm * K + gk]) : T(0);
+      if constexpr (GEN)
+        ra[e] = (abase[e] >= 0 && gk < K) ? A[abase[e] + gk * Qa] : T(0);
+      else
+        ra[e] = ok ? (TA ? A[gk * M + gm] : A[gm * K + gk]) : T(0);
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -81,7 +107,10 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
         gk = k0 + f % BK;
       }
       const bool ok = gn < N && gk < K;
-      rb[e] = ok ? (TB ? B[gn * K + gk] : B[gk * N + gn]) : T(0);
+      if constexpr (GEN)
+        rb[e] = (bbase[e] >= 0 && gk < K) ? B[bbase[e] + gk * Qb] : T(0);
+      else
+        rb[e] = ok ? (TB ? B[gn * K + gk] : B[gk * N + gn]) : T(0);
     }
   };
   auto store = [&]() {

@@ -13,8 +13,10 @@ namespace moa {
 
 // D (M x N) = op1-fold_l op2(A[i,l], B[l,j]) on the vector ALUs, ascending l.
 // tile: 8, 4 or 2 (register block per thread, side), 0 = automatic.
+// Qa, Qb: strided views for a contraction over any axis pair (A read as
+// (P_a, K, Qa), B as (P_b, K, Qb)); Qa = 1, Qb = N (or <= 0) is last-with-first.
 hipError_t launch_simt_inner(moa_dtype dt, moa_op op1, moa_op op2, const void *A, const void *B, void *D, int64_t M,
-                             int64_t K, int64_t N, int tile, hipStream_t s);
+                             int64_t K, int64_t N, int tile, hipStream_t s, int64_t Qa = 1, int64_t Qb = 0);
 
 // Few-row inner product (M <= kSkinnyMaxRows): the row form as an HBM stream,
 // every element of B read once, ascending-l fold (bit-exact, any op pair).
@@ -32,6 +34,10 @@ hipError_t launch_outer(moa_dtype dt, moa_op op, const void *A, const void *B, v
 // lda/ldb are implied by the stored shapes. tile: 0 automatic, 1 = 128x128, 2 = 64x64.
 hipError_t launch_gemm(moa_dtype dt, bool trans_a, bool trans_b, const void *A, const void *B, void *D, int64_t M,
                        int64_t K, int64_t N, int tile, hipStream_t s);
+
+// (+,*) on the matrix cores over the strided views above (general axes).
+hipError_t launch_gemm_strided(moa_dtype dt, const void *A, const void *B, void *D, int64_t M, int64_t K, int64_t N,
+                               int64_t Qa, int64_t Qb, hipStream_t s);
 
 // Fill n elements of dtype dt at p with the identity of op (empty fold).
 hipError_t launch_fill_identity(moa_dtype dt, moa_op op, void *p, int64_t n, hipStream_t s);

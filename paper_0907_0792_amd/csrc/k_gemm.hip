@@ -11,24 +11,26 @@
 // the next panel is fetched into registers while the current one is
 // multiplied. trans_a / trans_b read A stored K x M or B stored N x K, which
 // is how the backward pass contracts over permuted axes without a transposed
-// copy.
+// copy; the GEN variants read the strided (P, K, Q) views of a contraction
+// over any axis pair.
 #include "common.hpp"
 #include "gemm_tile.hpp"
 #include "internal.hpp"
 
 namespace moa {
 
-template <typename T, bool TA, bool TB, int WBM, int WBN>
+template <typename T, bool TA, bool TB, int WBM, int WBN, bool GEN>
 __global__ __launch_bounds__(256, 2) void k_gemm(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
-                                                  int64_t M, int64_t K, int64_t N, int64_t tiles_m,
-                                                  int64_t tiles_n) {
+                                                  int64_t M, int64_t K, int64_t N, int64_t tiles_m, int64_t tiles_n,
+                                                  int64_t Qa, int64_t Qb) {
   int64_t tm, tn;
   grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
-  gemm_tile<T, TA, TB, WBM, WBN>(A, B, D, M, K, N, tm * 32 * WBM, tn * 32 * WBN);
+  gemm_tile<T, TA, TB, WBM, WBN, 16, GEN>(A, B, D, M, K, N, tm * 32 * WBM, tn * 32 * WBN, Qa, Qb);
 }
 
-template <typename T, bool TA, bool TB>
-static hipError_t launch_t(const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile, hipStream_t s) {
+template <typename T, bool TA, bool TB, bool GEN>
+static hipError_t launch_t(const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile, int64_t Qa,
+                           int64_t Qb, hipStream_t s) {
   if (tile == 0) {
     const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
     tile = big >= 512 ? 1 : 2;
@@ -36,33 +38,50 @@ static hipError_t launch_t(const T *A, const T *B, T *D, int64_t M, int64_t K, i
   if (tile == 1) {
     const int64_t tmn = (M + 127) / 128, tnn = (N + 127) / 128;
     if (tmn * tnn > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_gemm<T, TA, TB, 4, 4>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K, N,
-                       tmn, tnn);
+    hipLaunchKernelGGL((k_gemm<T, TA, TB, 4, 4, GEN>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K,
+                       N, tmn, tnn, Qa, Qb);
   } else {
     const int64_t tmn = (M + 63) / 64, tnn = (N + 63) / 64;
     if (tmn * tnn > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_gemm<T, TA, TB, 2, 2>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K, N,
-                       tmn, tnn);
+    hipLaunchKernelGGL((k_gemm<T, TA, TB, 2, 2, GEN>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K,
+                       N, tmn, tnn, Qa, Qb);
   }
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool GEN>
 static hipError_t launch_tt(bool ta, bool tb, const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile,
-                            hipStream_t s) {
-  if (!ta && !tb) return launch_t<T, false, false>(A, B, D, M, K, N, tile, s);
-  if (ta && !tb) return launch_t<T, true, false>(A, B, D, M, K, N, tile, s);
-  if (!ta && tb) return launch_t<T, false, true>(A, B, D, M, K, N, tile, s);
-  return launch_t<T, true, true>(A, B, D, M, K, N, tile, s);
+                            int64_t Qa, int64_t Qb, hipStream_t s) {
+  if (!ta && !tb) return launch_t<T, false, false, GEN>(A, B, D, M, K, N, tile, Qa, Qb, s);
+  if (ta && !tb) return launch_t<T, true, false, GEN>(A, B, D, M, K, N, tile, Qa, Qb, s);
+  if (!ta && tb) return launch_t<T, false, true, GEN>(A, B, D, M, K, N, tile, Qa, Qb, s);
+  return launch_t<T, true, true, GEN>(A, B, D, M, K, N, tile, Qa, Qb, s);
 }
 
 hipError_t launch_gemm(moa_dtype dt, bool trans_a, bool trans_b, const void *A, const void *B, void *D, int64_t M,
                        int64_t K, int64_t N, int tile, hipStream_t s) {
   if (M == 0 || N == 0) return hipSuccess;
   if (dt == MOA_F64)
-    return launch_tt<double>(trans_a, trans_b, (const double *)A, (const double *)B, (double *)D, M, K, N, tile, s);
+    return launch_tt<double, false>(trans_a, trans_b, (const double *)A, (const double *)B, (double *)D, M, K, N, tile,
+                                    1, 1, s);
   if (dt == MOA_F32)
-    return launch_tt<float>(trans_a, trans_b, (const float *)A, (const float *)B, (float *)D, M, K, N, tile, s);
+    return launch_tt<float, false>(trans_a, trans_b, (const float *)A, (const float *)B, (float *)D, M, K, N, tile, 1,
+                                   1, s);
+  return hipErrorInvalidValue;
+}
+
+// Contraction over any axis pair: A, B read through their (P, K, Q) views.
+// Lanes run along i when A's inner extent Qa exceeds 1 and along k when B's
+// inner extent Qb is 1, so neighbouring lanes read neighbouring addresses.
+hipError_t launch_gemm_strided(moa_dtype dt, const void *A, const void *B, void *D, int64_t M, int64_t K, int64_t N,
+                               int64_t Qa, int64_t Qb, hipStream_t s) {
+  if (M == 0 || N == 0) return hipSuccess;
+  if (Qa <= 0 || Qb <= 0) return hipErrorInvalidValue;
+  const bool ta = Qa != 1, tb = Qb == 1;
+  if (dt == MOA_F64)
+    return launch_tt<double, true>(ta, tb, (const double *)A, (const double *)B, (double *)D, M, K, N, 0, Qa, Qb, s);
+  if (dt == MOA_F32)
+    return launch_tt<float, true>(ta, tb, (const float *)A, (const float *)B, (float *)D, M, K, N, 0, Qa, Qb, s);
   return hipErrorInvalidValue;
 }
 

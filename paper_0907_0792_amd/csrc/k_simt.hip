@@ -5,6 +5,11 @@
 // A is the flattened M x K view of rho A, B the K x N view of rho B, D the
 // M x N view of the result (row-major throughout; the rank only changes how
 // the same flat vectors are read, as in the MoA code fragment of Appendix A).
+// For a contraction over other axes, A is read as (P_a, K, Q_a) and B as
+// (P_b, K, Q_b) with row i = p * Q_a + q and column j = p' * Q_b + q':
+//     A[i, l] = A[(i / Q_a) * K * Q_a + l * Q_a + i % Q_a],
+//     B[l, j] = B[(j / Q_b) * K * Q_b + l * Q_b + j % Q_b],
+// which is the last-with-first case for Q_a = 1, Q_b = N.
 //
 // Layout of the work: the paper builds one row of the result at a time from
 // contiguous rows of B, each scaled by an element of A (Section I). Here a
@@ -27,7 +32,7 @@ namespace moa {
 template <typename T, int OP1, int OP2, int TM, int TN>
 __global__ __launch_bounds__(256) void k_simt_inner(const T *__restrict__ A, const T *__restrict__ B,
                                                     T *__restrict__ D, int64_t M, int64_t K, int64_t N,
-                                                    int64_t tiles_m, int64_t tiles_n) {
+                                                    int64_t tiles_m, int64_t tiles_n, int64_t Qa, int64_t Qb) {
   constexpr int BM = 16 * TM, BN = 16 * TN, BK = 16;
   constexpr int PAD = 16 / sizeof(T);
   __shared__ __attribute__((aligned(16))) T As[BK][BM + PAD];
@@ -51,16 +56,23 @@ __global__ __launch_bounds__(256) void k_simt_inner(const T *__restrict__ A, con
 #pragma unroll
     for (int p = 0; p < (BM * BK) / 256; ++p) {
       const int idx = tid + 256 * p;
-      const int r = idx / BK, c = idx % BK;
+      // Neighbouring lanes take neighbouring addresses: along k for the
+      // plain view, along i when A's inner extent Qa exceeds 1.
+      const int r = Qa == 1 ? idx / BK : idx % BM, c = Qa == 1 ? idx % BK : idx / BM;
       const int64_t gm = m0 + r, gk = k0 + c;
-      As[c][r] = (gm < M && gk < K) ? A[gm * K + gk] : T(0);
+      int64_t off = gm * K + gk;
+      if (Qa != 1) off = (gm / Qa) * K * Qa + gk * Qa + gm % Qa;
+      As[c][r] = (gm < M && gk < K) ? A[off] : T(0);
     }
 #pragma unroll
     for (int p = 0; p < (BN * BK) / 256; ++p) {
       const int idx = tid + 256 * p;
-      const int r = idx / BN, c = idx % BN;
+      // Along j, except when B's inner extent Qb is 1 (then along k).
+      const int r = Qb == 1 ? idx % BK : idx / BN, c = Qb == 1 ? idx / BK : idx % BN;
       const int64_t gk = k0 + r, gn = n0 + c;
-      Bs[r][c] = (gk < K && gn < N) ? B[gk * N + gn] : T(0);
+      int64_t off = gk * N + gn;
+      if (Qb != N) off = (gn / Qb) * K * Qb + gk * Qb + gn % Qb;
+      Bs[r][c] = (gk < K && gn < N) ? B[off] : T(0);
     }
     __syncthreads();
     const int kmax = (K - k0) < BK ? (int)(K - k0) : BK;
@@ -128,23 +140,23 @@ __global__ __launch_bounds__(256) void k_simt_inner(const T *__restrict__ A, con
 
 template <typename T, int OP1, int OP2>
 static hipError_t launch_tiles(const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile,
-                               hipStream_t s) {
+                               int64_t Qa, int64_t Qb, hipStream_t s) {
   int64_t tm, tn;
   if (tile == 8) {
     tm = (M + 127) / 128;
     tn = (N + 127) / 128;
     hipLaunchKernelGGL((k_simt_inner<T, OP1, OP2, 8, 8>), dim3((unsigned)(tm * tn)), dim3(256), 0, s, A, B, D, M, K,
-                       N, tm, tn);
+                       N, tm, tn, Qa, Qb);
   } else if (tile == 4) {
     tm = (M + 63) / 64;
     tn = (N + 63) / 64;
     hipLaunchKernelGGL((k_simt_inner<T, OP1, OP2, 4, 4>), dim3((unsigned)(tm * tn)), dim3(256), 0, s, A, B, D, M, K,
-                       N, tm, tn);
+                       N, tm, tn, Qa, Qb);
   } else {
     tm = (M + 31) / 32;
     tn = (N + 31) / 32;
     hipLaunchKernelGGL((k_simt_inner<T, OP1, OP2, 2, 2>), dim3((unsigned)(tm * tn)), dim3(256), 0, s, A, B, D, M, K,
-                       N, tm, tn);
+                       N, tm, tn, Qa, Qb);
   }
   return hipGetLastError();
 }
@@ -161,43 +173,43 @@ static int pick_tile(int64_t M, int64_t N) {
 
 template <typename T, int OP1>
 static hipError_t dispatch_op2(moa_op op2, const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile,
-                               hipStream_t s) {
+                               int64_t Qa, int64_t Qb, hipStream_t s) {
   switch (op2) {
-    case MOA_ADD: return launch_tiles<T, OP1, MOA_ADD>(A, B, D, M, K, N, tile, s);
-    case MOA_SUB: return launch_tiles<T, OP1, MOA_SUB>(A, B, D, M, K, N, tile, s);
-    case MOA_MUL: return launch_tiles<T, OP1, MOA_MUL>(A, B, D, M, K, N, tile, s);
-    case MOA_MAX: return launch_tiles<T, OP1, MOA_MAX>(A, B, D, M, K, N, tile, s);
-    case MOA_MIN: return launch_tiles<T, OP1, MOA_MIN>(A, B, D, M, K, N, tile, s);
+    case MOA_ADD: return launch_tiles<T, OP1, MOA_ADD>(A, B, D, M, K, N, tile, Qa, Qb, s);
+    case MOA_SUB: return launch_tiles<T, OP1, MOA_SUB>(A, B, D, M, K, N, tile, Qa, Qb, s);
+    case MOA_MUL: return launch_tiles<T, OP1, MOA_MUL>(A, B, D, M, K, N, tile, Qa, Qb, s);
+    case MOA_MAX: return launch_tiles<T, OP1, MOA_MAX>(A, B, D, M, K, N, tile, Qa, Qb, s);
+    case MOA_MIN: return launch_tiles<T, OP1, MOA_MIN>(A, B, D, M, K, N, tile, Qa, Qb, s);
     default: break;
   }
   if constexpr (T(1) / 2 == 0) {
     switch (op2) {
-      case MOA_AND: return launch_tiles<T, OP1, MOA_AND>(A, B, D, M, K, N, tile, s);
-      case MOA_OR: return launch_tiles<T, OP1, MOA_OR>(A, B, D, M, K, N, tile, s);
-      case MOA_XOR: return launch_tiles<T, OP1, MOA_XOR>(A, B, D, M, K, N, tile, s);
+      case MOA_AND: return launch_tiles<T, OP1, MOA_AND>(A, B, D, M, K, N, tile, Qa, Qb, s);
+      case MOA_OR: return launch_tiles<T, OP1, MOA_OR>(A, B, D, M, K, N, tile, Qa, Qb, s);
+      case MOA_XOR: return launch_tiles<T, OP1, MOA_XOR>(A, B, D, M, K, N, tile, Qa, Qb, s);
       default: break;
     }
   } else {
-    if (op2 == MOA_DIV) return launch_tiles<T, OP1, MOA_DIV>(A, B, D, M, K, N, tile, s);
+    if (op2 == MOA_DIV) return launch_tiles<T, OP1, MOA_DIV>(A, B, D, M, K, N, tile, Qa, Qb, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T>
 static hipError_t dispatch_op1(moa_op op1, moa_op op2, const T *A, const T *B, T *D, int64_t M, int64_t K,
-                               int64_t N, int tile, hipStream_t s) {
+                               int64_t N, int tile, int64_t Qa, int64_t Qb, hipStream_t s) {
   switch (op1) {
-    case MOA_ADD: return dispatch_op2<T, MOA_ADD>(op2, A, B, D, M, K, N, tile, s);
-    case MOA_MUL: return dispatch_op2<T, MOA_MUL>(op2, A, B, D, M, K, N, tile, s);
-    case MOA_MAX: return dispatch_op2<T, MOA_MAX>(op2, A, B, D, M, K, N, tile, s);
-    case MOA_MIN: return dispatch_op2<T, MOA_MIN>(op2, A, B, D, M, K, N, tile, s);
+    case MOA_ADD: return dispatch_op2<T, MOA_ADD>(op2, A, B, D, M, K, N, tile, Qa, Qb, s);
+    case MOA_MUL: return dispatch_op2<T, MOA_MUL>(op2, A, B, D, M, K, N, tile, Qa, Qb, s);
+    case MOA_MAX: return dispatch_op2<T, MOA_MAX>(op2, A, B, D, M, K, N, tile, Qa, Qb, s);
+    case MOA_MIN: return dispatch_op2<T, MOA_MIN>(op2, A, B, D, M, K, N, tile, Qa, Qb, s);
     default: break;
   }
   if constexpr (T(1) / 2 == 0) {
     switch (op1) {
-      case MOA_AND: return dispatch_op2<T, MOA_AND>(op2, A, B, D, M, K, N, tile, s);
-      case MOA_OR: return dispatch_op2<T, MOA_OR>(op2, A, B, D, M, K, N, tile, s);
-      case MOA_XOR: return dispatch_op2<T, MOA_XOR>(op2, A, B, D, M, K, N, tile, s);
+      case MOA_AND: return dispatch_op2<T, MOA_AND>(op2, A, B, D, M, K, N, tile, Qa, Qb, s);
+      case MOA_OR: return dispatch_op2<T, MOA_OR>(op2, A, B, D, M, K, N, tile, Qa, Qb, s);
+      case MOA_XOR: return dispatch_op2<T, MOA_XOR>(op2, A, B, D, M, K, N, tile, Qa, Qb, s);
       default: break;
     }
   }
@@ -205,16 +217,18 @@ static hipError_t dispatch_op1(moa_op op1, moa_op op2, const T *A, const T *B, T
 }
 
 hipError_t launch_simt_inner(moa_dtype dt, moa_op op1, moa_op op2, const void *A, const void *B, void *D, int64_t M,
-                             int64_t K, int64_t N, int tile, hipStream_t s) {
+                             int64_t K, int64_t N, int tile, hipStream_t s, int64_t Qa, int64_t Qb) {
   if (M == 0 || N == 0) return hipSuccess;
+  if (Qb <= 0) Qb = N;
+  if (Qa <= 0) Qa = 1;
   if (tile <= 0) tile = pick_tile(M, N);
   switch (dt) {
     case MOA_F64:
-      return dispatch_op1<double>(op1, op2, (const double *)A, (const double *)B, (double *)D, M, K, N, tile, s);
+      return dispatch_op1<double>(op1, op2, (const double *)A, (const double *)B, (double *)D, M, K, N, tile, Qa, Qb, s);
     case MOA_F32:
-      return dispatch_op1<float>(op1, op2, (const float *)A, (const float *)B, (float *)D, M, K, N, tile, s);
+      return dispatch_op1<float>(op1, op2, (const float *)A, (const float *)B, (float *)D, M, K, N, tile, Qa, Qb, s);
     case MOA_I32:
-      return dispatch_op1<int32_t>(op1, op2, (const int32_t *)A, (const int32_t *)B, (int32_t *)D, M, K, N, tile, s);
+      return dispatch_op1<int32_t>(op1, op2, (const int32_t *)A, (const int32_t *)B, (int32_t *)D, M, K, N, tile, Qa, Qb, s);
   }
   return hipErrorInvalidValue;
 }

@@ -128,6 +128,40 @@ moa_status flatten_outer(moa_shape a, moa_shape b, Flat *f) {
   return MOA_OK;
 }
 
+// Contraction of axis ax_a of A with axis ax_b of B: A is read as
+// (Pa, K, Qa) and B as (Pb, K, Qb); the result is (Pa Qa) x (Pb Qb).
+struct FlatAxes {
+  Flat f;
+  int64_t Pa, Qa, Pb, Qb;
+};
+
+moa_status flatten_axes(moa_shape a, int32_t ax_a, moa_shape b, int32_t ax_b, FlatAxes *g) {
+  moa_status st;
+  if ((st = check_shape(a, "A", 1)) != MOA_OK) return st;
+  if ((st = check_shape(b, "B", 1)) != MOA_OK) return st;
+  if (ax_a < 0 || ax_a >= a.rank) return fail(MOA_ERR_ARG, "axis %d of A outside [0, %d)", ax_a, a.rank);
+  if (ax_b < 0 || ax_b >= b.rank) return fail(MOA_ERR_ARG, "axis %d of B outside [0, %d)", ax_b, b.rank);
+  if (a.dims[ax_a] != b.dims[ax_b])
+    return fail(MOA_ERR_SHAPE, "contracted extents differ: rhoA[%d] = %lld, rhoB[%d] = %lld", ax_a,
+                (long long)a.dims[ax_a], ax_b, (long long)b.dims[ax_b]);
+  Flat &f = g->f;
+  if (!checked_prod(a.dims, ax_a, &g->Pa) || !checked_prod(a.dims + ax_a + 1, a.rank - ax_a - 1, &g->Qa) ||
+      !checked_prod(b.dims, ax_b, &g->Pb) || !checked_prod(b.dims + ax_b + 1, b.rank - ax_b - 1, &g->Qb) ||
+      !checked_prod(a.dims, a.rank, &f.nA) || !checked_prod(b.dims, b.rank, &f.nB))
+    return fail(MOA_ERR_SIZE, "element count overflows int64");
+  f.K = a.dims[ax_a];
+  // Pa Qa <= nA and Pb Qb <= nB unless K = 0, so check those products too.
+  if ((g->Qa != 0 && g->Pa > INT64_MAX / g->Qa) || (g->Qb != 0 && g->Pb > INT64_MAX / g->Qb))
+    return fail(MOA_ERR_SIZE, "element count overflows int64");
+  f.M = g->Pa * g->Qa;
+  f.N = g->Pb * g->Qb;
+  if (f.N != 0 && f.M > INT64_MAX / f.N) return fail(MOA_ERR_SIZE, "result element count overflows int64");
+  f.nD = f.M * f.N;
+  const int64_t lim = INT64_MAX / 8;
+  if (f.nA > lim || f.nB > lim || f.nD > lim) return fail(MOA_ERR_SIZE, "byte size overflows int64");
+  return MOA_OK;
+}
+
 bool overlaps(const void *p, int64_t np, const void *q, int64_t nq) {
   if (np == 0 || nq == 0 || !p || !q) return false;
   const uintptr_t a0 = (uintptr_t)p, a1 = a0 + (uintptr_t)np;
@@ -142,6 +176,27 @@ moa_status check_ptrs(const Flat &f, size_t es, const void *A, const void *B, co
   const int64_t bA = f.nA * (int64_t)es, bB = f.nB * (int64_t)es, bD = f.nD * (int64_t)es;
   if (overlaps(D, bD, A, bA) || overlaps(D, bD, B, bB)) return fail(MOA_ERR_ALIAS, "result overlaps an input");
   return MOA_OK;
+}
+
+
+// Launch D = A (op1 . op2) B over the (Pa, K, Qa) . (Pb, K, Qb) views
+// (Qa = 1, Qb = N: last axis of A with first axis of B). f.nD > 0.
+moa_status run_inner(const Flat &f, int64_t Qa, int64_t Qb, const void *A, const void *B, void *D, moa_op op1,
+                     moa_op op2, moa_dtype dt, uint32_t flags, hipStream_t s) {
+  if (f.K == 0) return hip_status(moa::launch_fill_identity(dt, op1, D, f.nD, s), "identity fill");
+  const bool plain = Qa == 1 && Qb == f.N;
+  // Few result rows and long rows of B: the row-form stream reads B once.
+  if (plain && f.M <= moa::kSkinnyMaxRows && f.N >= 4096)
+    return hip_status(moa::launch_skinny_inner(dt, op1, op2, A, B, D, f.M, f.K, f.N, s), "inner (few rows)");
+  const bool mfma = op1 == MOA_ADD && op2 == MOA_MUL && dt != MOA_I32 && !(flags & MOA_FLAG_SEQUENTIAL_FOLD);
+  if (mfma) {
+    // A is M x K (Qa = 1) or K x M (Pa = 1); B is K x N (Pb = 1) or N x K (Qb = 1).
+    const bool a_mat = Qa == 1 || Qa == f.M, b_mat = Qb == f.N || Qb == 1;
+    if (a_mat && b_mat)
+      return hip_status(moa::launch_gemm(dt, Qa != 1, Qb != f.N, A, B, D, f.M, f.K, f.N, 0, s), "inner (+,*)");
+    return hip_status(moa::launch_gemm_strided(dt, A, B, D, f.M, f.K, f.N, Qa, Qb, s), "inner (+,*), strided");
+  }
+  return hip_status(moa::launch_simt_inner(dt, op1, op2, A, B, D, f.M, f.K, f.N, 0, s, Qa, Qb), "inner");
 }
 
 }  // namespace
@@ -204,19 +259,41 @@ moa_status moa_inner_ex(moa_shape sa, const void *A, moa_shape sb, const void *B
   if (st != MOA_OK) return st;
   if ((st = check_ptrs(f, elem_size(dt), A, B, D)) != MOA_OK) return st;
   if (f.nD == 0) return MOA_OK;
-  hipStream_t s = (hipStream_t)stream;
-  if (f.K == 0) return hip_status(moa::launch_fill_identity(dt, op1, D, f.nD, s), "identity fill");
-  // Few result rows and long rows of B: the row-form stream reads B once.
-  if (f.M <= moa::kSkinnyMaxRows && f.N >= 4096)
-    return hip_status(moa::launch_skinny_inner(dt, op1, op2, A, B, D, f.M, f.K, f.N, s), "inner (few rows)");
-  const bool mfma = op1 == MOA_ADD && op2 == MOA_MUL && dt != MOA_I32 && !(flags & MOA_FLAG_SEQUENTIAL_FOLD);
-  if (mfma) return hip_status(moa::launch_gemm(dt, false, false, A, B, D, f.M, f.K, f.N, 0, s), "inner (+,*)");
-  return hip_status(moa::launch_simt_inner(dt, op1, op2, A, B, D, f.M, f.K, f.N, 0, s), "inner");
+  return run_inner(f, 1, f.N, A, B, D, op1, op2, dt, flags, (hipStream_t)stream);
 }
 
 moa_status moa_inner(moa_shape sa, const void *A, moa_shape sb, const void *B, moa_op op1, moa_op op2, moa_dtype dt,
                      void *D, void *stream) {
   return moa_inner_ex(sa, A, sb, B, op1, op2, dt, D, 0u, stream);
+}
+
+moa_status moa_inner_axes_shape(moa_shape a, int32_t ax_a, moa_shape b, int32_t ax_b, int64_t *out_dims,
+                                int32_t *out_rank) {
+  if (!out_dims || !out_rank) return fail(MOA_ERR_NULL, "output shape pointer is NULL");
+  FlatAxes g;
+  moa_status st = flatten_axes(a, ax_a, b, ax_b, &g);
+  if (st != MOA_OK) return st;
+  int r = 0;
+  for (int i = 0; i < a.rank; ++i)
+    if (i != ax_a) out_dims[r++] = a.dims[i];
+  for (int i = 0; i < b.rank; ++i)
+    if (i != ax_b) out_dims[r++] = b.dims[i];
+  *out_rank = r;
+  return MOA_OK;
+}
+
+moa_status moa_inner_axes(moa_shape sa, const void *A, int32_t ax_a, moa_shape sb, const void *B, int32_t ax_b,
+                          moa_op op1, moa_op op2, moa_dtype dt, void *D, uint32_t flags, void *stream) {
+  if (!valid_dtype(dt)) return fail(MOA_ERR_DTYPE, "unknown dtype %d", (int)dt);
+  if (!is_fold_op(op1, dt)) return fail(MOA_ERR_OP, "op1 %d is not a fold operation for this dtype", (int)op1);
+  if (!is_elem_op(op2, dt)) return fail(MOA_ERR_OP, "op2 %d is not defined for this dtype", (int)op2);
+  if (flags & ~MOA_FLAG_SEQUENTIAL_FOLD) return fail(MOA_ERR_ARG, "unknown flags 0x%x", flags);
+  FlatAxes g;
+  moa_status st = flatten_axes(sa, ax_a, sb, ax_b, &g);
+  if (st != MOA_OK) return st;
+  if ((st = check_ptrs(g.f, elem_size(dt), A, B, D)) != MOA_OK) return st;
+  if (g.f.nD == 0) return MOA_OK;
+  return run_inner(g.f, g.Qa, g.Qb, A, B, D, op1, op2, dt, flags, (hipStream_t)stream);
 }
 
 moa_status moa_outer(moa_shape sa, const void *A, moa_shape sb, const void *B, moa_op op, moa_dtype dt, void *C,

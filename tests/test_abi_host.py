@@ -174,3 +174,37 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(moa, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         moa.lib()
+
+
+@pytest.mark.parametrize("sa,ax_a,sb,ax_b", [((2, 3, 4), 1, (3, 2), 0), ((2, 3, 4), 0, (5, 2), 1),
+                                             ((3, 2), 0, (2, 4, 3), 2), ((4,), 0, (4,), 0), ((2, 0, 3), 2, (3, 5), 0)])
+def test_inner_axes_shape(sa, ax_a, sb, ax_b):
+    want = oracle.inner_axes(np.zeros(sa), ax_a, np.zeros(sb), ax_b).shape
+    assert moa.inner_axes_shape(sa, ax_a, sb, ax_b) == want
+    # Negative axes count from the end, as in numpy.
+    assert moa.inner_axes_shape(sa, ax_a - len(sa), sb, ax_b - len(sb)) == want
+
+
+def test_inner_axes_validation_before_launch():
+    L = moa.lib()
+    S = moa.STATUS
+    sh = moa._shape
+    z = ctypes.c_void_p
+    A, B, D = z(0x100000), z(0x200000), z(0x300000)
+    add, mul = moa.OPS["add"], moa.OPS["mul"]
+
+    def call(sa, ax_a, sb, ax_b, op1=add, op2=mul, dt=0, d=D, flags=0):
+        return S[L.moa_inner_axes(sh(sa), A, ax_a, sh(sb), B, ax_b, op1, op2, dt, d, flags, z(0))]
+
+    assert call((4, 8), 2, (4, 2), 0) == "MOA_ERR_ARG"
+    assert call((4, 8), -1, (8, 2), 0) == "MOA_ERR_ARG"
+    assert call((4, 8), 0, (8, 2), 0) == "MOA_ERR_SHAPE"
+    assert call((4, 8), 0, (2, 4), 1, dt=9) == "MOA_ERR_DTYPE"
+    assert call((4, 8), 0, (2, 4), 1, op1=moa.OPS["sub"]) == "MOA_ERR_OP"
+    assert call((4, 8), 0, (2, 4), 1, flags=4) == "MOA_ERR_ARG"
+    assert call((4, 8), 0, (2, 4), 1, d=z(0)) == "MOA_ERR_NULL"
+    assert call((4, 8), 0, (2, 4), 1, d=z(0x100000 + 64)) == "MOA_ERR_ALIAS"
+    assert call((), 0, (2, 4), 1) == "MOA_ERR_RANK"
+    assert call((8, 0), 0, (2, 8), 1, d=z(0)) == "MOA_OK"      # empty result: no launch
+    big = 2 ** 40
+    assert call((big, 2, big), 1, (2, 3), 0) == "MOA_ERR_SIZE"

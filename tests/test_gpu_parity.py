@@ -473,3 +473,81 @@ def test_errors_on_device_tensors():
     with pytest.raises(moa.MoaError) as e:
         moa.inner(a, gpu(np.ones((4, 2))), "sub", "mul")
     assert moa.STATUS[e.value.status] == "MOA_ERR_OP"
+
+
+# ---------------------------------------------------------------------------
+# Contraction over any axis pair, read in place through (P, K, Q) views.
+
+AXES_CASES = [
+    ((7, 45, 33), 1, (20, 45, 13), 1),     # general strides on both sides, ragged tiles
+    ((45, 150), 0, (130, 45), 1),          # A stored K x M, B stored N x K
+    ((3, 70, 2, 5), 1, (70, 140), 0),      # A strided, B plain
+    ((90, 37), 1, (11, 37, 12), 1),        # A plain, B strided
+    ((17, 130), 0, (17,), 0),              # A stored K x M, vector result
+]
+
+
+def _moved(a, ax_a, b, ax_b):
+    return np.moveaxis(a, ax_a, -1), np.moveaxis(b, ax_b, 0)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32, np.int32])
+def test_inner_axes_all_pairs_bit_exact(dt):
+    rng = np.random.default_rng(41)
+    folds = FOLD_I if dt == np.int32 else FOLD_F
+    elems = ELEM_I if dt == np.int32 else ELEM_F
+    for sa, ax_a, sb, ax_b in AXES_CASES[:3]:
+        say("axes", dt.__name__, sa, ax_a, sb, ax_b)
+        a, b = rand(rng, sa, dt), rand(rng, sb, dt)
+        ga, gb = gpu(a), gpu(b)
+        for op1 in folds:
+            for op2 in elems:
+                got = host(moa.inner_axes(ga, gb, (ax_a, ax_b), op1, op2, flags=moa.FLAG_SEQUENTIAL_FOLD))
+                eq(got, oracle.inner_axes(a, ax_a, b, ax_b, op1, op2, mode="native"))
+
+
+@pytest.mark.parametrize("dt,tol", [(np.float64, 1e-13), (np.float32, 1e-5)])
+def test_inner_axes_mfma(dt, tol):
+    rng = np.random.default_rng(42)
+    for sa, ax_a, sb, ax_b in AXES_CASES:
+        say("axes (+,*)", dt.__name__, sa, ax_a, sb, ax_b)
+        a, b = rand(rng, sa, dt), rand(rng, sb, dt)
+        got = host(moa.inner_axes(gpu(a), gpu(b), (ax_a, ax_b)))
+        ref = oracle.inner_dot2(*_moved(a.astype(np.float64), ax_a, b.astype(np.float64), ax_b))
+        assert got.shape == ref.shape
+        assert nerr(got, ref) <= tol
+
+
+def test_inner_axes_mfma_exact_integers():
+    # Small integers: every partial sum is exact, so any summation order gives
+    # the oracle's value bit for bit.
+    rng = np.random.default_rng(43)
+    for sa, ax_a, sb, ax_b in AXES_CASES:
+        a = mi.small_int_f64(rng, sa, 8)
+        b = mi.small_int_f64(rng, sb, 8)
+        eq(host(moa.inner_axes(gpu(a), gpu(b), (ax_a, ax_b))), oracle.inner_axes(a, ax_a, b, ax_b))
+
+
+def test_inner_axes_last_with_first_equals_inner():
+    rng = np.random.default_rng(44)
+    a, b = rand(rng, (40, 9, 33), np.float64), rand(rng, (33, 70), np.float64)
+    ga, gb = gpu(a), gpu(b)
+    eq(host(moa.inner_axes(ga, gb, (-1, 0))), host(moa.inner(ga, gb)))
+    eq(host(moa.inner_axes(ga, gb, (2, 0), "max", "add")), host(moa.inner(ga, gb, "max", "add")))
+
+
+def test_inner_axes_large_sampled():
+    # 3072 x 512 . 512 x 1280 through general strides on both operands.
+    rng = np.random.default_rng(45)
+    a = mi.uniform_f64(rng, (64, 512, 48))
+    b = mi.uniform_f64(rng, (32, 512, 40))
+    got = host(moa.inner_axes(gpu(a), gpu(b), (1, 1))).reshape(3072, 1280)
+    am, bm = _moved(a, 1, b, 1)
+    rows = np.sort(rng.choice(3072, 24, replace=False))
+    ref = oracle.inner_dot2(am, bm, rows=rows).reshape(len(rows), 1280)
+    assert nerr(got[rows], ref) <= 1e-13
+    at, bt = rand(rng, (300, 64, 7), np.int32), rand(rng, (9, 64, 150), np.int32)
+    got = host(moa.inner_axes(gpu(at), gpu(bt), (1, 1), "max", "add")).reshape(2100, 1350)
+    rows = np.sort(rng.choice(2100, 24, replace=False))
+    ref = oracle.inner_axes(at, 1, bt, 1, "max", "add", rows=rows).reshape(len(rows), 1350)
+    eq(got[rows], ref)

@@ -447,3 +447,56 @@ def test_split_chosen_parameters_meet_tolerance_on_workload_distribution():
     ref = oracle.inner_dot2(a, b)
     err = oracle.normwise_error(oracle.split_inner(a, b, nslices=5, beta=9), ref)
     assert err <= 1e-12, err
+
+
+# --------------------------------------------------------------------------
+# Contraction over any axis pair (Section I: Eq. inner as a tensor contraction;
+# index maps of Section II.D).
+
+AXES_SHAPES = [((2, 3, 4), 1, (3, 2), 0), ((2, 3, 4), 0, (5, 2), 1), ((3, 2), 0, (2, 4, 3), 2),
+               ((4,), 0, (2, 4, 1), 1), ((2, 2, 3), 2, (3,), 0), ((1, 3, 2), 1, (2, 3, 2), 1)]
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32, np.int32])
+def test_inner_axes_matches_brute_force(dt):
+    rng = np.random.default_rng(31)
+    pairs = ([("add", "mul"), ("max", "add"), ("min", "sub"), ("xor", "and")] if dt == np.int32 else
+             [("add", "mul"), ("max", "add"), ("min", "sub"), ("mul", "div")])
+    for sa, ax_a, sb, ax_b in AXES_SHAPES:
+        a = _rand(rng, sa, dt)
+        b = _rand(rng, sb, dt)
+        for op1, op2 in pairs:
+            _equal(oracle.inner_axes(a, ax_a, b, ax_b, op1, op2, mode="native"),
+                   brute.inner_axes(a, ax_a, b, ax_b, op1, op2))
+
+
+def test_inner_axes_is_tensordot():
+    rng = np.random.default_rng(32)
+    for sa, ax_a, sb, ax_b in AXES_SHAPES + [((5, 6, 7, 3), 2, (2, 7, 4), 1), ((9, 8), 0, (8, 9), 1)]:
+        ai = mi.uniform_i32(rng, sa)
+        bi = mi.uniform_i32(rng, sb)
+        want = np.tensordot(ai.astype(np.int64), bi.astype(np.int64), axes=([ax_a], [ax_b])).astype(np.int32)
+        assert np.array_equal(oracle.inner_axes(ai, ax_a, bi, ax_b), want)
+        a = mi.uniform_f64(rng, sa)
+        b = mi.uniform_f64(rng, sb)
+        want = np.tensordot(a, b, axes=([ax_a], [ax_b]))
+        assert oracle.normwise_error(oracle.inner_axes(a, ax_a, b, ax_b), want) < 1e-15
+
+
+def test_inner_axes_last_with_first_is_inner():
+    rng = np.random.default_rng(33)
+    a = mi.uniform_f64(rng, (3, 4, 5))
+    b = mi.uniform_f64(rng, (5, 2))
+    _equal(oracle.inner_axes(a, -1, b, 0, "max", "add"), oracle.inner(a, b, "max", "add"))
+
+
+def test_inner_axes_operand_swap_transposes_result():
+    # For a commutative op2, swapping the operands swaps the two groups of
+    # free axes of the result and nothing else.
+    rng = np.random.default_rng(34)
+    a = _rand(rng, (2, 5, 3), np.int32)
+    b = _rand(rng, (4, 5), np.int32)
+    for op1, op2 in [("add", "mul"), ("max", "min"), ("or", "xor")]:
+        d = oracle.inner_axes(a, 1, b, 1, op1, op2)            # axes (2, 3, 4)
+        e = oracle.inner_axes(b, 1, a, 1, op1, op2)            # axes (4, 2, 3)
+        _equal(np.moveaxis(e, 0, -1), d)
