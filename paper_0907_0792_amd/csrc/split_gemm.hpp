@@ -24,12 +24,13 @@
 // (K not a multiple of 256) folds levels 0..3 every 64 k.
 //
 // A and B chunks are copied global -> LDS with global_load_lds_dwordx4 (no
-// staging registers). An LDS stage holds one 16-wide k block of the tile's
+// staging registers). An LDS stage holds kSKB 16-wide k blocks of the tile's
 // slices; kNBuf stages rotate, so copies run kNBuf - 1 stages ahead of the
 // MFMAs and one barrier per stage suffices: the buffer refilled at stage st
 // was last read at stage st - 1, which every wave has left once it passes the
 // barrier of stage st. Each wave reads its fragments as conflict-free
-// ds_read_b128.
+// ds_read_b128. Two stages of two k blocks measured slightly faster than four
+// of one (half the barriers, twice the MFMAs between them).
 #pragma once
 
 #include <utility>
@@ -40,9 +41,15 @@ namespace moa {
 namespace split {
 
 constexpr int kBeta = 9;    // BF16 digit width: |digit| <= 2^(beta-1) = 256
-constexpr int kSKB = 1;       // 16-wide k blocks per LDS stage
-constexpr int kNBuf = 4;      // LDS stages in rotation
-constexpr int kCycleKB = 16;  // unrolled cycle: 256 k (a multiple of kNBuf)
+constexpr int kSKB = 2;       // 16-wide k blocks per LDS stage
+constexpr int kNBuf = 2;      // LDS stages in rotation
+constexpr int kCycleKB = 16;  // unrolled cycle: 256 k
+constexpr int kCycleSt = kCycleKB / kSKB;
+static_assert(kCycleKB % kSKB == 0 && 4 % kSKB == 0, "a 64-k tail step must be whole stages");
+
+// s_waitcnt immediate: wait until at most n vector-memory operations of this
+// wave are outstanding (vmcnt split over bits 3:0 and 15:14; lgkm/exp: no wait).
+__host__ __device__ constexpr int vmcnt_imm(int n) { return 0x0F70 | (n & 15) | ((n >> 4) << 14); }
 
 // Fold period of level d in k blocks (0 = only at the end).
 __host__ __device__ constexpr int period_kb(int d) {
@@ -168,48 +175,49 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
 
   const int64_t nst = KB / kSKB;
   // Stage st: wait for its copies, barrier, refill the buffer of stage st - 1
-  // with stage st + kNBuf - 1, then multiply.
-  auto stage = [&](int64_t st, auto qc) {
+  // with stage st + kNBuf - 1, then multiply its kSKB k blocks. I = position
+  // of the stage in the 256-k cycle, or -1 in the tail.
+  auto stage = [&](int64_t st, auto ic) {
+    constexpr int I = decltype(ic)::value;
     const int buf = (int)(st % kNBuf);
-    // Copies of stages st+1 and st+2 may stay in flight; near the end of K
-    // (fewer stages ahead) wait for everything.
-    if (st + 2 < nst) {
+    // Issued so far: stages up to st + kNBuf - 2. Stage st must be complete;
+    // the kNBuf - 2 after it may stay in flight (all of them near the end).
+    if (kNBuf > 2 && st + kNBuf - 2 < nst) {
       if (wave < C::EXTRA)
-        __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * C::MAX_WAVE));
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm((kNBuf - 2) * C::MAX_WAVE));
       else
-        __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * C::PER_WAVE));
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm((kNBuf - 2) * C::PER_WAVE));
     } else {
-      __builtin_amdgcn_s_waitcnt(0x0F70);
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
     }
     // A plain barrier, not __syncthreads(): its fence would also wait for the
     // copies still in flight. LDS is coherent within the workgroup.
     __builtin_amdgcn_s_barrier();
     if (st + kNBuf - 1 < nst) issue_stage(st + kNBuf - 1, (int)((st + kNBuf - 1) % kNBuf));
-    mma_kb(buf, 0, qc);
+    [&]<int... J>(std::integer_sequence<int, J...>) {
+      (mma_kb(buf, J, std::integral_constant<int, I < 0 ? -1 : I * kSKB + J>{}), ...);
+    }(std::make_integer_sequence<int, kSKB>{});
   };
 
-  static_assert(kNBuf == 4, "the wait counts above assume four buffers");
   for (int i = 0; i < kNBuf - 1; ++i)
     if (i < nst) issue_stage(i, i);
-  const int64_t ncyc = nst / kCycleKB;
+  const int64_t ncyc = nst / kCycleSt;
   int64_t st = 0;
   for (int64_t cyc = 0; cyc < ncyc; ++cyc) {
     [&]<int... I>(std::integer_sequence<int, I...>) {
       (stage(st + I, std::integral_constant<int, I>{}), ...);
-    }(std::make_integer_sequence<int, kCycleKB>{});
-    st += kCycleKB;
+    }(std::make_integer_sequence<int, kCycleSt>{});
+    st += kCycleSt;
   }
   if (st < nst) {
-    // Tail: levels 0..3 restart from zero and fold every 64 k (four stages).
+    // Tail: levels 0..3 restart from zero and fold every 64 k.
 #pragma unroll
     for (int d = 0; d < S && d < 4; ++d)
 #pragma unroll
       for (int j = 0; j < WN; ++j) acc[d][j] = zero16;
-    for (; st < nst; st += 4) {
-      stage(st, std::integral_constant<int, -1>{});
-      stage(st + 1, std::integral_constant<int, -1>{});
-      stage(st + 2, std::integral_constant<int, -1>{});
-      stage(st + 3, std::integral_constant<int, -1>{});
+    for (; st < nst; st += 4 / kSKB) {
+#pragma unroll
+      for (int i = 0; i < 4 / kSKB; ++i) stage(st + i, std::integral_constant<int, -1>{});
 #pragma unroll
       for (int d = 0; d < S && d < 4; ++d) {
         fold_level(d);
