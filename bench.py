@@ -191,7 +191,7 @@ def other_workload(args):
                     gops=round(2.0 * m * k * n / (ms * 1e-3) / 1e9, 2),
                     config={"workload": "FP64 (+,*) %d x %d . %d x %d (the paper's m x 128 . 128 x n matrix product)"
                                         % (m, k, k, n), "m": m, "k": k, "n": n},
-                    roofline={"bound": "hbm", "kernel": "k_skinny<double,add,mul,%d>" % m, "achieved": round(gbs, 2),
+                    roofline={"bound": "hbm", "kernel": "k_skinny<double, add, mul, MR=%d, R=4>" % m, "achieved": round(gbs, 2),
                               "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                               "traffic": None})
     if w == "tropical":

@@ -138,6 +138,25 @@ def test_few_rows_stream_all_pairs_bit_exact(dt):
                 eq(host(moa.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
 
 
+@pytest.mark.parametrize("dt", [np.float64, np.float32, np.int32])
+def test_few_rows_wide_runs_ragged(dt):
+    # Rows long enough for four 16-byte runs per thread, with a partial last
+    # workgroup (N not a multiple of its span) and with unaligned rows
+    # (N not a multiple of the vector width: scalar loads everywhere).
+    rng = np.random.default_rng(110)
+    vec = 16 // np.dtype(dt).itemsize
+    span = 256 * vec * 4
+    base = 512 * span
+    for M, K, N in [(3, 5, base + vec), (4, 3, base + span + 1), (1, 2, base)]:
+        a = rand(rng, (M, K), dt)
+        b = rand(rng, (K, N), dt)
+        ga, gb = gpu(a), gpu(b)
+        for op1, op2 in ([("add", "mul"), ("max", "add"), ("xor", "and")] if dt == np.int32 else
+                         [("add", "mul"), ("max", "add"), ("min", "div")]):
+            say("few rows wide", np.dtype(dt).name, M, K, N, op1, op2)
+            eq(host(moa.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
+
+
 def test_few_rows_paper_workload_full():
     # Section II.B: A m x 128 (m = 4), B 128 x n, n = 2^22; every row checked.
     a, b = mi.workload_skinny()
