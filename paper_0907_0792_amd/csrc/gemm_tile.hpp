@@ -36,7 +36,10 @@ struct Mfma16<float> {
 // B[k, j] = B[(j / Qb) K Qb + k Qb + j % Qb]; TA, TB then only choose which
 // index runs fastest across threads (TA: i, else k; TB: k, else j), so that
 // neighbouring lanes read neighbouring addresses.
-template <typename T, bool TA, bool TB, int WBM, int WBN, int BK = 16, bool GEN = false>
+// SKIP: a wave issues no MFMA for its 16 x 16 blocks that lie wholly past
+// M or N (small problems in a fixed tile: the matrix-core work then follows
+// the problem's extents in steps of 16 instead of the tile's).
+template <typename T, bool TA, bool TB, int WBM, int WBN, int BK = 16, bool GEN = false, bool SKIP = false>
 __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
                                           int64_t M, int64_t K, int64_t N, int64_t m0, int64_t n0, int64_t Qa = 1,
                                           int64_t Qb = 1) {
@@ -48,8 +51,15 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
   __shared__ T As[BK][BM + PAD];
   __shared__ T Bs[BK][BN + PAD];
 
-  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int tid = threadIdx.x, lane = tid % kWave, wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const int wm = wave / 2, wn = wave % 2;
+  // Blocks of this wave inside the problem (all of them unless SKIP).
+  int nbm = WBM, nbn = WBN;
+  if constexpr (SKIP) {
+    const int64_t rm = M - (m0 + wm * (BM / 2)), rn = N - (n0 + wn * (BN / 2));
+    nbm = rm <= 0 ? 0 : (rm >= 16 * WBM ? WBM : (int)((rm + 15) / 16));
+    nbn = rn <= 0 ? 0 : (rn >= 16 * WBN ? WBN : (int)((rn + 15) / 16));
+  }
 
   acc_t acc[WBM][WBN];
 #pragma unroll
@@ -149,7 +159,8 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
 #pragma unroll
       for (int i = 0; i < WBM; ++i)
 #pragma unroll
-        for (int j = 0; j < WBN; ++j) acc[i][j] = MF::run(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < WBN; ++j)
+          if (!SKIP || (i < nbm && j < nbn)) acc[i][j] = MF::run(a[i], b[j], acc[i][j]);
     }
   }
   __syncthreads();  // LDS is reused by the caller's next tile
