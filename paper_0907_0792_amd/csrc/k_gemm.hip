@@ -25,7 +25,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const T *__restrict__ A, const 
                                                   int64_t Qa, int64_t Qb) {
   int64_t tm, tn;
   grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
-  gemm_tile<T, TA, TB, WBM, WBN, 16, GEN>(A, B, D, M, K, N, tm * 32 * WBM, tn * 32 * WBN, Qa, Qb);
+  // FP32 MFMAs run at twice the FP64 rate: 32-wide k panels halve the
+  // barriers and panel stores per flop.
+  gemm_tile<T, TA, TB, WBM, WBN, sizeof(T) == 4 ? 32 : 16, GEN>(A, B, D, M, K, N, tm * 32 * WBM, tn * 32 * WBN, Qa, Qb);
 }
 
 template <typename T, bool TA, bool TB, bool GEN>
