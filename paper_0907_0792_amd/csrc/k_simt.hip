@@ -20,8 +20,8 @@
 // reused TN (resp. TM) times. The fold runs in ascending l from the identity
 // of op1, one IEEE operation per step, so FP results equal a sequential fold
 // bit for bit. Folds whose result is association-independent (all int32 folds,
-// FP max/min) fold two terms at a time, which lets the compiler emit
-// three-operand max/min/add.
+// FP max/min) fold two terms at a time: one three-operand max/min/add per
+// pair for int32.
 #pragma clang fp contract(off)
 
 #include "common.hpp"
@@ -94,8 +94,7 @@ __global__ __launch_bounds__(256) void k_simt_inner(const T *__restrict__ A, con
         for (int i = 0; i < TM; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j)
-            acc[i][j] = apply_op<OP1>(acc[i][j],
-                                      apply_op<OP1>(apply_op<OP2>(a0[i], b0[j]), apply_op<OP2>(a1[i], b1[j])));
+            acc[i][j] = fold_pair<OP1>(acc[i][j], apply_op<OP2>(a0[i], b0[j]), apply_op<OP2>(a1[i], b1[j]));
       }
     } else if (kmax == BK) {
 #pragma unroll
