@@ -53,26 +53,42 @@ __global__ __launch_bounds__(256) void k_simt_inner(const T *__restrict__ A, con
 
   for (int64_t k0 = 0; k0 < K; k0 += BK) {
     // Stage A[m0:m0+BM, k0:k0+BK] transposed into As[k][m], B[k0:k0+BK, n0:n0+BN] into Bs[k][n].
+    // The view test is wave-uniform and sits outside the unrolled loops, so
+    // the plain layout's staging carries no code of the strided one.
+    if (Qa == 1) {
 #pragma unroll
-    for (int p = 0; p < (BM * BK) / 256; ++p) {
-      const int idx = tid + 256 * p;
-      // Neighbouring lanes take neighbouring addresses: along k for the
-      // plain view, along i when A's inner extent Qa exceeds 1.
-      const int r = Qa == 1 ? idx / BK : idx % BM, c = Qa == 1 ? idx % BK : idx / BM;
-      const int64_t gm = m0 + r, gk = k0 + c;
-      int64_t off = gm * K + gk;
-      if (Qa != 1) off = (gm / Qa) * K * Qa + gk * Qa + gm % Qa;
-      As[c][r] = (gm < M && gk < K) ? A[off] : T(0);
+      for (int p = 0; p < (BM * BK) / 256; ++p) {
+        const int idx = tid + 256 * p;
+        const int r = idx / BK, c = idx % BK;  // lanes along k
+        const int64_t gm = m0 + r, gk = k0 + c;
+        As[c][r] = (gm < M && gk < K) ? A[gm * K + gk] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < (BM * BK) / 256; ++p) {
+        const int idx = tid + 256 * p;
+        const int r = idx % BM, c = idx / BM;  // lanes along i, contiguous when Qa > 1
+        const int64_t gm = m0 + r, gk = k0 + c;
+        As[c][r] = (gm < M && gk < K) ? A[(gm / Qa) * K * Qa + gk * Qa + gm % Qa] : T(0);
+      }
     }
+    if (Qb == N) {
 #pragma unroll
-    for (int p = 0; p < (BN * BK) / 256; ++p) {
-      const int idx = tid + 256 * p;
-      // Along j, except when B's inner extent Qb is 1 (then along k).
-      const int r = Qb == 1 ? idx % BK : idx / BN, c = Qb == 1 ? idx / BK : idx % BN;
-      const int64_t gk = k0 + r, gn = n0 + c;
-      int64_t off = gk * N + gn;
-      if (Qb != N) off = (gn / Qb) * K * Qb + gk * Qb + gn % Qb;
-      Bs[r][c] = (gk < K && gn < N) ? B[off] : T(0);
+      for (int p = 0; p < (BN * BK) / 256; ++p) {
+        const int idx = tid + 256 * p;
+        const int r = idx / BN, c = idx % BN;  // lanes along j
+        const int64_t gk = k0 + r, gn = n0 + c;
+        Bs[r][c] = (gk < K && gn < N) ? B[gk * N + gn] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < (BN * BK) / 256; ++p) {
+        const int idx = tid + 256 * p;
+        // Along j, except when B's inner extent Qb is 1 (then along k).
+        const int r = Qb == 1 ? idx % BK : idx / BN, c = Qb == 1 ? idx / BK : idx % BN;
+        const int64_t gk = k0 + r, gn = n0 + c;
+        Bs[r][c] = (gk < K && gn < N) ? B[(gn / Qb) * K * Qb + gk * Qb + gn % Qb] : T(0);
+      }
     }
     __syncthreads();
     const int kmax = (K - k0) < BK ? (int)(K - k0) : BK;
