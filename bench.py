@@ -178,6 +178,21 @@ def other_workload(args):
                     roofline={"bound": "mfma", "kernel": "k_gemm<double, TA=1, TB=0, 4x4, GEN=1>", "achieved": round(t, 3),
                               "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(t / PEAK_FP64_TFLOPS, 4),
                               "traffic": None})
+    if w == "fewcols":
+        a_h, b_h = mi.workload_fewcols()
+        a, b = put(a_h), put(b_h)
+        m, k, n = a_h.shape[0], a_h.shape[1], b_h.shape[1]
+        out = torch.empty((m, n), dtype=torch.int32, device=dev)
+        ms, wall = _time_events(lambda: moa.inner(a, b, "max", "add", out=out), args.steps, args.warmup)
+        nbytes = 4.0 * (m * k + k * n + m * n)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return dict(base, metric="few-column inner product GB/s", value=round(gbs, 2), unit="GB/s",
+                    ms_per_step=round(ms, 4), dtype="int32", gops=round(2.0 * m * k * n / (ms * 1e-3) / 1e9, 2),
+                    config={"workload": "int32 (max,+) %d x %d . %d x %d (wavefront-reduced fold over l)"
+                                        % (m, k, k, n), "m": m, "k": k, "n": n},
+                    roofline={"bound": "hbm", "kernel": "k_fewcols<int, max, add, NC=8>", "achieved": round(gbs, 2),
+                              "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                              "traffic": None})
     if w == "skinny":
         a_h, b_h = mi.workload_skinny()
         a, b = put(a_h), put(b_h)
@@ -274,7 +289,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="split",
                     choices=["split", "plain64", "rank5", "tropical", "outer", "batch", "grad", "small", "skinny",
-                             "axes"])
+                             "axes", "fewcols"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()

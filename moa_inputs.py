@@ -186,6 +186,12 @@ def workload_axes(rng=None, sa=(16, 2048, 512), sb=(16, 2048, 512)):
     return uniform_f64(rng, sa), uniform_f64(rng, sb)
 
 
+def workload_fewcols(rng=None, m=65536, k=4096, n=8):
+    """int32 (max,+) with few result columns: A m x k, B k x n, entries U{-1000..1000}."""
+    rng = rng or rng_for(RANK_GENERAL, salt=7)
+    return uniform_i32(rng, (m, k)), uniform_i32(rng, (k, n))
+
+
 def workload_grad(rng=None, sa=(32, 128, 512), sb=(512, 64, 64)):
     rng = rng or rng_for(DIFFERENTIATION)
     a = uniform_f32(rng, sa)

@@ -24,6 +24,14 @@ constexpr int64_t kSkinnyMaxRows = 8;
 hipError_t launch_skinny_inner(moa_dtype dt, moa_op op1, moa_op op2, const void *A, const void *B, void *D, int64_t M,
                                int64_t K, int64_t N, hipStream_t s);
 
+// Few-column inner product (N <= kFewColsMax) for association-independent
+// folds (int32, FP max/min): the fold over l split across a wave's lanes and
+// combined by a wavefront reduction.
+constexpr int64_t kFewColsMax = 16;
+bool fewcols_applies(moa_dtype dt, moa_op op1, int64_t M, int64_t K, int64_t N);
+hipError_t launch_fewcols_inner(moa_dtype dt, moa_op op1, moa_op op2, const void *A, const void *B, void *D,
+                                int64_t M, int64_t K, int64_t N, hipStream_t s);
+
 // C (NA x NB) = op(A[i], B[j]).
 hipError_t launch_outer(moa_dtype dt, moa_op op, const void *A, const void *B, void *C, int64_t NA, int64_t NB,
                         hipStream_t s);

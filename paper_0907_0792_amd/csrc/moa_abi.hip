@@ -188,6 +188,9 @@ moa_status run_inner(const Flat &f, int64_t Qa, int64_t Qb, const void *A, const
   // Few result rows and long rows of B: the row-form stream reads B once.
   if (plain && f.M <= moa::kSkinnyMaxRows && f.N >= 4096)
     return hip_status(moa::launch_skinny_inner(dt, op1, op2, A, B, D, f.M, f.K, f.N, s), "inner (few rows)");
+  // Few columns, association-independent fold: lanes share the fold over l.
+  if (plain && moa::fewcols_applies(dt, op1, f.M, f.K, f.N))
+    return hip_status(moa::launch_fewcols_inner(dt, op1, op2, A, B, D, f.M, f.K, f.N, s), "inner (few columns)");
   const bool mfma = op1 == MOA_ADD && op2 == MOA_MUL && dt != MOA_I32 && !(flags & MOA_FLAG_SEQUENTIAL_FOLD);
   if (mfma) {
     // A is M x K (Qa = 1) or K x M (Pa = 1); B is K x N (Pb = 1) or N x K (Qb = 1).

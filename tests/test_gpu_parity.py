@@ -157,6 +157,32 @@ def test_few_rows_wide_runs_ragged(dt):
             eq(host(moa.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
 
 
+@pytest.mark.parametrize("dt", [np.int32, np.float64, np.float32])
+def test_few_columns_wave_reduction_bit_exact(dt):
+    # N <= 16 and an association-independent fold: the fold over l is split
+    # across the lanes of a wave and combined by a wavefront reduction.
+    rng = np.random.default_rng(111)
+    folds = FOLD_I if dt == np.int32 else ["max", "min"]
+    elems = ELEM_I if dt == np.int32 else ELEM_F
+    for M, K, N in [(300, 1000, 1), (257, 777, 3), (5, 4100, 16), (1, 256, 7), (33, 300, 4), (9, 513, 9)]:
+        a = rand(rng, (M, K), dt)
+        b = rand(rng, (K, N), dt)
+        ga, gb = gpu(a), gpu(b)
+        for op1 in folds:
+            for op2 in elems:
+                say("few columns", np.dtype(dt).name, M, K, N, op1, op2)
+                eq(host(moa.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
+
+
+def test_few_columns_workload_sampled():
+    # int32 (max,+) <65536 4096> . <4096 8>: rows checked against the oracle.
+    a, b = mi.workload_fewcols()
+    say("few columns 65536 x 4096 . 4096 x 8")
+    d = host(moa.inner(gpu(a), gpu(b), "max", "add"))
+    rows = np.sort(np.random.default_rng(112).choice(a.shape[0], 64, replace=False))
+    eq(d[rows], oracle.inner(a, b, "max", "add", rows=rows))
+
+
 def test_few_rows_paper_workload_full():
     # Section II.B: A m x 128 (m = 4), B 128 x n, n = 2^22; every row checked.
     a, b = mi.workload_skinny()
