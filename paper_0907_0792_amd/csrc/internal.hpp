@@ -39,7 +39,8 @@ hipError_t launch_outer(moa_dtype dt, moa_op op, const void *A, const void *B, v
 // D (M x N) = A (M x K) * B (K x N) on the matrix cores, FP64 or FP32.
 // trans_a: A is stored K x M (row-major) instead of M x K.
 // trans_b: B is stored N x K instead of K x N.
-// lda/ldb are implied by the stored shapes. tile: 0 automatic, 1 = 128x128, 2 = 64x64.
+// lda/ldb are implied by the stored shapes. tile: 0 automatic, 1 = 128x128, 2 = 64x64,
+// 3 = 32x32.
 hipError_t launch_gemm(moa_dtype dt, bool trans_a, bool trans_b, const void *A, const void *B, void *D, int64_t M,
                        int64_t K, int64_t N, int tile, hipStream_t s);
 

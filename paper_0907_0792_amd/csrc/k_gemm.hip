@@ -34,10 +34,18 @@ template <typename T, bool TA, bool TB, bool GEN>
 static hipError_t launch_t(const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile, int64_t Qa,
                            int64_t Qb, hipStream_t s) {
   if (tile == 0) {
+    // The largest tile that still gives the CUs enough workgroups: 128 x 128
+    // from 512 tiles up, 64 x 64 from 256 (one per CU), else 32 x 32.
     const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
-    tile = big >= 512 ? 1 : 2;
+    const int64_t mid = ((M + 63) / 64) * ((N + 63) / 64);
+    tile = big >= 512 ? 1 : mid >= 256 ? 2 : 3;
   }
-  if (tile == 1) {
+  if (tile == 3) {
+    const int64_t tmn = (M + 31) / 32, tnn = (N + 31) / 32;
+    if (tmn * tnn > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_gemm<T, TA, TB, 1, 1, GEN>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K,
+                       N, tmn, tnn, Qa, Qb);
+  } else if (tile == 1) {
     const int64_t tmn = (M + 127) / 128, tnn = (N + 127) / 128;
     if (tmn * tnn > 0x7fffffff) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((k_gemm<T, TA, TB, 4, 4, GEN>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K,
