@@ -10,8 +10,10 @@ Entry points mirror the C ABI:
 
 * :func:`inner` / :func:`inner_ex` — generalized inner product
   ``D = A (op1 . op2) B`` (Section I, Eq. inner).
+* :func:`inner_axes` — the same contraction over any axis pair, read in place.
 * :func:`outer` — generalized outer product ``C = A op B`` (Section I, Eq. outer).
-* :func:`inner_split` — (+,*) FP64 at FP64 accuracy from BF16 slices.
+* :func:`inner_split` — (+,*) FP64 at FP64 accuracy from BF16 or INT8 slices
+  (:func:`split_prepare` / :func:`split_multiply` run its two stages apart).
 * :func:`inner_grad` — backward of the (+,*) inner product.
 * :class:`Batch` — many uneven (+,*) products in one persistent graph launch.
 * :class:`MoaInner` — ``torch.autograd.Function`` over inner / inner_grad.

@@ -6,8 +6,9 @@
 // M x K and K x N views.
 //
 // Workgroup = 4 waves (2 x 2), each owning a (16*WBM) x (16*WBN) block of D
-// as WBM x WBN 16x16 accumulator tiles. A and B panels of BK = 16 are staged
-// in LDS (k-major, so one fragment read is 16 contiguous elements per k row);
+// as WBM x WBN 16x16 accumulator tiles. A and B panels of BK = 16 k (32 for
+// FP32) are staged in LDS (k-major, so one fragment read is 16 contiguous
+// elements per k row);
 // the next panel is fetched into registers while the current one is
 // multiplied. trans_a / trans_b read A stored K x M or B stored N x K, which
 // is how the backward pass contracts over permuted axes without a transposed

@@ -69,7 +69,6 @@ struct Cfg {
   static constexpr int PER_WAVE = ST_CH / kWaves;                  // copies per stage, later waves
   static constexpr int MAX_WAVE = (ST_CH + kWaves - 1) / kWaves;  // copies per stage, first waves
   static constexpr int EXTRA = ST_CH % kWaves;                     // waves that issue MAX_WAVE
-  static constexpr size_t kLdsBytes = (size_t)kNBuf * ST_CH * 1024;
 };
 
 __device__ __forceinline__ floatx16 mfma_bf16(const bf16x8 &a, const bf16x8 &b, const floatx16 &c) {
