@@ -596,3 +596,62 @@ def test_inner_axes_large_sampled():
     rows = np.sort(rng.choice(2100, 24, replace=False))
     ref = oracle.inner_axes(at, 1, bt, 1, "max", "add", rows=rows).reshape(len(rows), 1350)
     eq(got[rows], ref)
+
+
+# ---------------------------------------------------------------------------
+# API corners: the two-stage split API, FP64 batches, non-default streams.
+
+def test_split_two_stage_api_matches_one_call():
+    # moa_inner_split_prepare + moa_inner_split_multiply run the same kernels
+    # as moa_inner_split: identical bits, and the oracle's scheme to 1e-14.
+    rng = np.random.default_rng(120)
+    a = mi.scaled_f64(rng, (200, 700))
+    b = mi.scaled_f64(rng, (700, 150))
+    ga, gb = gpu(a), gpu(b)
+    for fmt, S, beta in (("bf16", 5, 9), ("int8", 7, 7)):
+        say("split two-stage", fmt)
+        one = host(moa.inner_split(ga, gb, fmt, S))
+        ws = torch.empty(moa.split_workspace_bytes(a.shape, b.shape, fmt, S), dtype=torch.uint8, device=DEV)
+        out = torch.full((200, 150), float("nan"), dtype=torch.float64, device=DEV)
+        moa.split_prepare(ga, gb, ws, fmt, S)
+        moa.split_multiply(a.shape, b.shape, out, ws, fmt, S)
+        two = host(out)
+        eq(two, one)
+        assert nerr(two, oracle.split_inner(a, b, nslices=S, beta=beta)) <= 1e-14
+        # The multiply stage alone can be replayed on the same workspace.
+        out.fill_(float("nan"))
+        moa.split_multiply(a.shape, b.shape, out, ws, fmt, S)
+        eq(host(out), one)
+
+
+def test_batch_fp64():
+    rng = np.random.default_rng(121)
+    shapes = mi.batch_shapes(rng, 300)
+    probs = [(sa, sb, mi.uniform_f64(rng, sa), mi.uniform_f64(rng, sb)) for sa, sb in shapes]
+    As = [gpu(a) for _, _, a, _ in probs]
+    Bs = [gpu(b) for _, _, _, b in probs]
+    Ds = [torch.full(moa.inner_shape(sa, sb), float("nan"), dtype=torch.float64, device=DEV)
+          for sa, sb, _, _ in probs]
+    say("batch fp64 300")
+    bt = moa.Batch(As, Bs, Ds)
+    bt.run()
+    torch.cuda.synchronize()
+    for (sa, sb, a, b), d in zip(probs, Ds):
+        assert nerr(d.cpu().numpy(), oracle.inner_dot2(a, b)) <= 1e-13, (sa, sb)
+    bt.close()
+
+
+def test_non_default_stream():
+    # Work is enqueued on the caller's current stream; results are complete
+    # once that stream is synchronised.
+    rng = np.random.default_rng(122)
+    a = rand(rng, (300, 500), np.int32)
+    b = rand(rng, (500, 200), np.int32)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ga, gb = gpu(a), gpu(b)
+        d = moa.inner(ga, gb, "max", "add")
+        c = moa.outer(ga[:3], gb[0], "sub")
+    s.synchronize()
+    eq(d.cpu().numpy(), oracle.inner(a, b, "max", "add"))
+    eq(c.cpu().numpy(), oracle.outer(a[:3], b[0], "sub"))
