@@ -94,7 +94,8 @@ int32_t moa_abi_version(void);
 
 /* ---------------------------------------------------------------------------
  * Shape algebra (host only, no GPU needed).
- * out_dims must hold MOA_MAX_RANK (inner) or 2*MOA_MAX_RANK (outer) entries.
+ * out_dims must hold 2*MOA_MAX_RANK entries (an inner result has rank up to
+ * 2*MOA_MAX_RANK - 2, an outer one up to 2*MOA_MAX_RANK).
  */
 moa_status moa_inner_shape(moa_shape a, moa_shape b, int64_t *out_dims, int32_t *out_rank);
 moa_status moa_outer_shape(moa_shape a, moa_shape b, int64_t *out_dims, int32_t *out_rank);
@@ -132,6 +133,7 @@ moa_status moa_inner_ex(moa_shape sa, const void *A, moa_shape sb, const void *B
  * rhoA[ax_a] = rhoB[ax_b] (else MOA_ERR_SHAPE); ops, dtypes, flags, aliasing
  * and the fold order as for moa_inner_ex.
  */
+/* Result shape of moa_inner_axes; out_dims must hold 2*MOA_MAX_RANK entries. */
 moa_status moa_inner_axes_shape(moa_shape a, int32_t ax_a, moa_shape b, int32_t ax_b, int64_t *out_dims,
                                 int32_t *out_rank);
 moa_status moa_inner_axes(moa_shape sa, const void *A, int32_t ax_a, moa_shape sb, const void *B, int32_t ax_b,

@@ -132,7 +132,7 @@ def _dev_operands(*ts):
 
 
 def inner_shape(sa, sb):
-    out = (ctypes.c_int64 * MAX_RANK)()
+    out = (ctypes.c_int64 * (2 * MAX_RANK))()
     r = ctypes.c_int32()
     _check(lib().moa_inner_shape(_shape(sa), _shape(sb), out, ctypes.byref(r)))
     return tuple(out[i] for i in range(r.value))
@@ -144,7 +144,7 @@ def _axis(ax, rank):
 
 
 def inner_axes_shape(sa, ax_a, sb, ax_b):
-    out = (ctypes.c_int64 * MAX_RANK)()
+    out = (ctypes.c_int64 * (2 * MAX_RANK))()
     r = ctypes.c_int32()
     _check(lib().moa_inner_axes_shape(_shape(sa), _axis(ax_a, len(sa)), _shape(sb), _axis(ax_b, len(sb)), out,
                                       ctypes.byref(r)))

@@ -208,3 +208,14 @@ def test_inner_axes_validation_before_launch():
     assert call((8, 0), 0, (2, 8), 1, d=z(0)) == "MOA_OK"      # empty result: no launch
     big = 2 ** 40
     assert call((big, 2, big), 1, (2, 3), 0) == "MOA_ERR_SIZE"
+
+
+def test_inner_shape_of_two_rank16_operands():
+    # The result of an inner product of two rank-16 arrays has rank 30; the
+    # shape query must return all of it (out_dims holds 2 * MOA_MAX_RANK).
+    sa = (1, 2, 3) + (1,) * 12 + (4,)
+    sb = (4,) + (2,) * 14 + (5,)
+    got = moa.inner_shape(sa, sb)
+    assert got == sa[:-1] + sb[1:] and len(got) == 30
+    assert moa.inner_axes_shape(sa, 15, sb, 0) == got
+    assert moa.outer_shape((1,) * 16, (2,) * 16) == (1,) * 16 + (2,) * 16

@@ -655,3 +655,39 @@ def test_non_default_stream():
     s.synchronize()
     eq(d.cpu().numpy(), oracle.inner(a, b, "max", "add"))
     eq(c.cpu().numpy(), oracle.outer(a[:3], b[0], "sub"))
+
+
+def test_int32_wraparound_every_path():
+    # Large int32 entries: +, - and * overflow and must wrap exactly as the
+    # oracle's two's-complement arithmetic in every kernel that folds int32.
+    rng = np.random.default_rng(130)
+    big = lambda shape: rng.integers(-2**31, 2**31, size=shape, dtype=np.int64).astype(np.int32)
+    cases = [((70, 90), (90, 50)),          # register-blocked SIMT
+             ((3, 40), (40, 5000)),         # few rows, stream over B
+             ((40, 600), (600, 5)),         # few columns, wavefront reduction
+             ((2, 3, 7), (7, 2, 2))]        # rank 3, small
+    for sa, sb in cases:
+        a, b = big(sa), big(sb)
+        ga, gb = gpu(a), gpu(b)
+        for op1, op2 in [("add", "mul"), ("mul", "add"), ("add", "sub"), ("max", "mul"), ("xor", "mul")]:
+            say("int32 wrap", sa, sb, op1, op2)
+            eq(host(moa.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2))
+    a, b = big((33, 17)), big((9, 129))
+    for op in ("add", "sub", "mul"):
+        eq(host(moa.outer(gpu(a), gpu(b), op)), oracle.outer(a, b, op))
+
+
+def test_maximum_rank_and_unit_axes():
+    rng = np.random.default_rng(131)
+    sa = (1, 2, 1, 3, 1, 1, 2, 1, 1, 1, 1, 1, 1, 2, 1, 5)          # rank 16
+    sb = (5, 1, 1, 1, 1, 1, 1, 1, 2, 1, 1, 1, 1, 1, 1, 3)          # rank 16
+    a = rand(rng, sa, np.int32)
+    b = rand(rng, sb, np.int32)
+    d = host(moa.inner(gpu(a), gpu(b), "add", "mul"))
+    assert d.shape == sa[:-1] + sb[1:]
+    eq(d, oracle.inner(a, b, "add", "mul"))
+    with pytest.raises(moa.MoaError):
+        moa.inner(gpu(np.zeros((1,) * 17, np.int32)), gpu(np.zeros((1, 1), np.int32)))
+    x = rand(rng, (1, 1, 4), np.float64)
+    y = rand(rng, (4, 1, 1), np.float64)
+    eq(host(moa.inner(gpu(x), gpu(y), "max", "sub")), oracle.inner(x, y, "max", "sub", mode="native"))
