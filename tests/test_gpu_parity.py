@@ -691,3 +691,23 @@ def test_maximum_rank_and_unit_axes():
     x = rand(rng, (1, 1, 4), np.float64)
     y = rand(rng, (4, 1, 1), np.float64)
     eq(host(moa.inner(gpu(x), gpu(y), "max", "sub")), oracle.inner(x, y, "max", "sub", mode="native"))
+
+
+def test_plain_fp64_8192_sampled():
+    # The plain FP64 comparator of the split benchmark, at its full size.
+    a, b = mi.workload_split()
+    say("plain fp64 8192^3")
+    d = host(moa.inner(gpu(a), gpu(b)))
+    rows = np.sort(np.random.default_rng(140).choice(8192, 12, replace=False))
+    assert nerr(d[rows], oracle.inner_dot2(a, b, rows=rows)) <= 1e-13
+
+
+def test_axes_bench_config_sampled():
+    # <16 2048 512> . <16 2048 512> over axes (1, 1), as benchmarked.
+    a, b = mi.workload_axes()
+    say("axes <16 2048 512> . <16 2048 512>")
+    d = host(moa.inner_axes(gpu(a), gpu(b), (1, 1))).reshape(8192, 8192)
+    am, bm = np.moveaxis(a, 1, -1), np.moveaxis(b, 1, 0)
+    rows = np.sort(np.random.default_rng(141).choice(8192, 12, replace=False))
+    ref = oracle.inner_dot2(am, bm, rows=rows).reshape(len(rows), 8192)
+    assert nerr(d[rows], ref) <= 1e-13
