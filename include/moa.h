@@ -205,8 +205,9 @@ moa_status moa_inner_grad(moa_shape sa, const void *A, moa_shape sb, const void 
  * launch in a HIP graph on `stream`. The caller's A[i], B[i], D[i] (device
  * pointers, dtype dt = MOA_F32 or MOA_F64) must stay valid while the batch
  * exists; moa_batch_run replays the graph (one kernel launch). A batch owns
- * only its descriptor table, work counters and graph; moa_batch_free releases
- * them. Concurrent runs of the same batch race on its work counters.
+ * only its descriptor table, work list and graph; moa_batch_free releases
+ * them. A run keeps no state, but concurrent runs of one batch write the
+ * same D arrays.
  */
 typedef struct moa_batch moa_batch;
 moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A, const moa_shape *sb,

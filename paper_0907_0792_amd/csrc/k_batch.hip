@@ -2,11 +2,11 @@
 //
 // Each problem i is the (+,*) case of Eq. inner (Section I) on its own
 // flattened M_i x K_i . K_i x N_i view. The batch is cut into work items
-// (one output tile of one problem each); items are ordered by estimated cost,
-// largest first, and a persistent grid of workgroups pulls them from a device
-// counter, so the skew between large and small problems is absorbed at run
-// time. The counter resets itself (the last workgroup to finish zeroes it),
-// so the captured graph can be replayed with no memset node.
+// (one output tile of one problem each) ordered by estimated cost, largest
+// first, and a persistent grid (as many workgroups as fit on the GPU at once)
+// takes them round-robin, so each workgroup gets a similar mix of large and
+// small items. The launch has no state between replays, so the captured graph
+// replays as is.
 //
 // Tile variants (per problem, from the tile table):
 //   0: 32 x 32 tiles (one 16 x 16 MFMA block per wave)
@@ -38,7 +38,6 @@ struct moa_batch {
   int64_t items;
   moa::BatchDesc *d_desc;
   moa::BatchItem *d_items;
-  unsigned int *d_counters;  // [0] next item, [1] finished workgroups
   hipGraph_t graph;
   hipGraphExec_t exec;
   int grid;
@@ -63,15 +62,11 @@ int g_table[kBuckets] = {1, 1, 1, 1, 1, 1, 1, 1};
 
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_batch(const BatchDesc *__restrict__ desc,
-                                                   const BatchItem *__restrict__ items, int64_t n_items,
-                                                   unsigned int *__restrict__ counters) {
-  __shared__ int64_t s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&counters[0], 1u);
-    __syncthreads();
-    const int64_t it = s_item;
-    __syncthreads();
-    if (it >= n_items) break;
+                                                   const BatchItem *__restrict__ items, int64_t n_items) {
+  // Items are taken round-robin (costliest first): one shared counter for
+  // every item serialises ~n_items atomics on one address, which measured as
+  // ~15 us of fixed cost per item per workgroup.
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const BatchItem w = items[it];
     const BatchDesc p = desc[w.prob];
     const int side = (p.tile == 0) ? 32 : 64;
@@ -85,30 +80,23 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchDesc *__restrict__ 
       gemm_tile<T, false, false, 2, 2, 16, false, true>((const T *)p.A, (const T *)p.B, (T *)p.D, p.M, p.K, p.N,
                                                          tm * side, tn * side);
   }
-  // Every workgroup has taken its last item; the last one to get here
-  // re-arms the counters for the next replay.
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned int done = atomicAdd(&counters[1], 1u);
-    if (done == gridDim.x - 1) {
-      atomicExch(&counters[0], 0u);
-      atomicExch(&counters[1], 0u);
-    }
-  }
 }
 
-__global__ void k_zero_u32(unsigned int *p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
-}
 
+// As many workgroups as can be resident at once (CUs x occupancy): with
+// round-robin items, a workgroup that had to wait for a free slot would run
+// its share after everyone else.
+template <typename T>
 int persistent_grid() {
-  int dev = 0, cus = 256;
+  int dev = 0, cus = 256, per_cu = 4;
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
       cus = prop.multiProcessorCount;
   }
-  return cus * 4;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<T>, 256, 0) == hipSuccess && occ > 0) per_cu = occ;
+  return cus * per_cu;
 }
 
 moa_status hip_fail(hipError_t e, const char *what) {
@@ -123,7 +111,6 @@ void free_batch(moa_batch *b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_desc) (void)hipFree(b->d_desc);
   if (b->d_items) (void)hipFree(b->d_items);
-  if (b->d_counters) (void)hipFree(b->d_counters);
   delete b;
 }
 
@@ -201,10 +188,9 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
   b->dt = dt;
   b->n = n;
   b->items = (int64_t)items.size();
-  b->grid = persistent_grid();
+  b->grid = (dt == MOA_F32) ? persistent_grid<float>() : persistent_grid<double>();
   hipError_t e;
   hipStream_t cap = nullptr;
-  if ((e = hipMalloc(&b->d_counters, 4 * sizeof(unsigned int))) != hipSuccess) goto hip_error;
   if (n > 0 && (e = hipMalloc(&b->d_desc, sizeof(BatchDesc) * (size_t)n)) != hipSuccess) goto hip_error;
   if (!items.empty() && (e = hipMalloc(&b->d_items, sizeof(BatchItem) * items.size())) != hipSuccess) goto hip_error;
   if (n > 0 &&
@@ -213,20 +199,17 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
   if (!items.empty() && (e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(),
                                        hipMemcpyHostToDevice)) != hipSuccess)
     goto hip_error;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, (hipStream_t)stream, b->d_counters, 4);
-  if ((e = hipGetLastError()) != hipSuccess) goto hip_error;
-  if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) goto hip_error;
   // Capture the persistent launch on a private stream (capture is not allowed
   // on the legacy default stream); the graph is replayed on any stream.
   if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) goto hip_error;
   if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) goto hip_error;
   if (b->items > 0) {
     if (dt == MOA_F32)
-      hipLaunchKernelGGL(k_batch<float>, dim3((unsigned)b->grid), dim3(256), 0, cap, b->d_desc, b->d_items, b->items,
-                         b->d_counters);
+      hipLaunchKernelGGL(k_batch<float>, dim3((unsigned)b->grid), dim3(256), 0, cap, b->d_desc, b->d_items,
+                         b->items);
     else
       hipLaunchKernelGGL(k_batch<double>, dim3((unsigned)b->grid), dim3(256), 0, cap, b->d_desc, b->d_items,
-                         b->items, b->d_counters);
+                         b->items);
   }
   if ((e = hipStreamEndCapture(cap, &b->graph)) != hipSuccess) goto hip_error;
   if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) goto hip_error;
