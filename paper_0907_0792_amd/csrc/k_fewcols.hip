@@ -51,9 +51,16 @@ __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const 
 
   for (int64_t k0 = 0; k0 < K; k0 += kChunk) {
     const int kc = (K - k0) < kChunk ? (int)(K - k0) : kChunk;
-    // Stage rows k0 .. k0 + kc - 1 of B (one contiguous block of kc N).
+    // Stage rows k0 .. k0 + kc - 1 of B (one contiguous block of kc N):
+    // thread t takes column t % NP of rows t / NP, t / NP + 256 / NP, ...
+    // (NP = NC rounded up to a power of two, so no division by N).
     __syncthreads();
-    for (int f = tid; f < kc * N; f += 256) Bs[(f / N) * SB + f % N] = B[k0 * N + f];
+    {
+      constexpr int NP = NC <= 1 ? 1 : NC <= 2 ? 2 : NC <= 4 ? 4 : NC <= 8 ? 8 : 16;
+      const int c = tid % NP;
+      if (c < N)
+        for (int r = tid / NP; r < kc; r += 256 / NP) Bs[r * SB + c] = B[(k0 + r) * N + c];
+    }
     __syncthreads();
     // Lane q folds l = q, q + 64, q + 128, q + 192 of the chunk: each load of
     // an A row is 64 consecutive elements across the wave.
