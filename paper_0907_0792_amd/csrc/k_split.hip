@@ -101,26 +101,74 @@ __device__ __forceinline__ void digits8(const double v[8], int e, bf16x8 sig[S])
   }
 }
 
-// A slices: thread = (row block mb, k block kb, lane).
+// INT8 slices (MOA_SPLIT_INT8): signed digits of 7 bits, |digit| <= 64,
+// chunk = 64 lanes x 16 INT8 (a 32 x 32 operand of v_mfma_i32_32x32x32_i8,
+// lane l holding row/col l % 32 and k = 16 * (l / 32) .. + 15).
 template <int S>
+__device__ __forceinline__ void digits16_i8(const double v[16], int e, split::i8::intx4 sig[S]) {
+  constexpr int kB = split::i8::kBeta;
+#pragma unroll
+  for (int s = 0; s < S; ++s) sig[s] = split::i8::intx4{0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    double r = ldexp(v[q], kB - 1 - e);  // x * 2^(beta-1), exact
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double d = rint(r);
+      sig[s][q / 4] |= ((int)d & 0xff) << (8 * (q % 4));
+      r = (r - d) * (double)(1 << kB);
+    }
+  }
+}
+
+// A slices. A wave owns one chunk: row block mb (32 rows) and k block kb (CK =
+// 16 k for BF16, 32 for INT8). It first copies the 32 x CK block of A into its
+// own LDS region with row-contiguous loads (CK lanes per row, 64 / CK rows per
+// load), then each lane reads back the values of its operand slot (row l % 32,
+// k = CK / 2 * (l / 32) ..) and writes their digits. Loading A directly in the
+// operand layout would make every load instruction touch 64 rows.
+template <int S, bool I8>
 __global__ __launch_bounds__(256) void k_slice_a(const double *__restrict__ A, int64_t M, int64_t K,
                                                  const uint64_t *__restrict__ rowmax, int64_t KB, int64_t nchunks,
-                                                 bf16x8 *__restrict__ Apk) {
-  const int64_t blk = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;  // (mb, kb) pair index
-  if (blk >= nchunks) return;
-  const int lane = threadIdx.x % 64;
-  const int64_t mb = blk / KB, kb = blk % KB;
-  const int64_t row = mb * 32 + lane % 32;
-  const int64_t k0 = kb * 16 + (lane / 32) * 8;
-  double v[8];
+                                                 void *__restrict__ Apk) {
+  constexpr int CK = I8 ? 32 : 16, VL = CK / 2, RPL = kWave / CK;
+  constexpr int LS = CK + 2;  // padded row stride (doubles) of the staged block
+  __shared__ double tile[4][32 * LS];
+  const int lane = threadIdx.x % kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t blk = (int64_t)blockIdx.x * 4 + w;  // (mb, kb) pair index
+  const bool live = blk < nchunks;
+  const int64_t mb = live ? blk / KB : 0, kb = live ? blk % KB : 0;
+  double *T = tile[w];
+  if (live) {
+    const int64_t col = kb * CK + lane % CK;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = (row < M && k0 + q < K) ? A[row * K + k0 + q] : 0.0;
-  const int e = exponent_of_max(rowmax[row]);
-  bf16x8 sig[S];
-  digits8<S>(v, e, sig);
-  bf16x8 *dst = Apk + (blk * S) * 64 + lane;
+    for (int j = 0; j < 32 / RPL; ++j) {
+      const int r = j * RPL + lane / CK;
+      const int64_t row = mb * 32 + r;
+      T[r * LS + lane % CK] = (row < M && col < K) ? A[row * K + col] : 0.0;
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+  const int r = lane % 32, h = lane / 32;
+  double v[VL];
 #pragma unroll
-  for (int s = 0; s < S; ++s) dst[s * 64] = sig[s];
+  for (int q = 0; q < VL; ++q) v[q] = T[r * LS + h * VL + q];
+  const int e = exponent_of_max(rowmax[mb * 32 + r]);
+  if constexpr (I8) {
+    split::i8::intx4 sig[S];
+    digits16_i8<S>(v, e, sig);
+    split::i8::intx4 *dst = (split::i8::intx4 *)Apk + (blk * S) * 64 + lane;
+#pragma unroll
+    for (int s = 0; s < S; ++s) dst[s * 64] = sig[s];
+  } else {
+    bf16x8 sig[S];
+    digits8<S>(v, e, sig);
+    bf16x8 *dst = (bf16x8 *)Apk + (blk * S) * 64 + lane;
+#pragma unroll
+    for (int s = 0; s < S; ++s) dst[s * 64] = sig[s];
+  }
 }
 
 // B slices: thread = (column block nb, k block kb, lane).
@@ -145,47 +193,7 @@ __global__ __launch_bounds__(256) void k_slice_b(const double *__restrict__ B, i
   for (int s = 0; s < S; ++s) dst[s * 64] = sig[s];
 }
 
-// INT8 slices (MOA_SPLIT_INT8): signed digits of 7 bits, |digit| <= 64,
-// chunk = 64 lanes x 16 INT8 (a 32 x 32 operand of v_mfma_i32_32x32x32_i8,
-// lane l holding row/col l % 32 and k = 16 * (l / 32) .. + 15).
-template <int S>
-__device__ __forceinline__ void digits16_i8(const double v[16], int e, split::i8::intx4 sig[S]) {
-  constexpr int kB = split::i8::kBeta;
-#pragma unroll
-  for (int s = 0; s < S; ++s) sig[s] = split::i8::intx4{0, 0, 0, 0};
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    double r = ldexp(v[q], kB - 1 - e);  // x * 2^(beta-1), exact
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const double d = rint(r);
-      sig[s][q / 4] |= ((int)d & 0xff) << (8 * (q % 4));
-      r = (r - d) * (double)(1 << kB);
-    }
-  }
-}
-
-template <int S>
-__global__ __launch_bounds__(256) void k_slice_a_i8(const double *__restrict__ A, int64_t M, int64_t K,
-                                                    const uint64_t *__restrict__ rowmax, int64_t KB, int64_t nchunks,
-                                                    split::i8::intx4 *__restrict__ Apk) {
-  const int64_t blk = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (blk >= nchunks) return;
-  const int lane = threadIdx.x % 64;
-  const int64_t mb = blk / KB, kb = blk % KB;
-  const int64_t row = mb * 32 + lane % 32;
-  const int64_t k0 = kb * 32 + (lane / 32) * 16;
-  double v[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) v[q] = (row < M && k0 + q < K) ? A[row * K + k0 + q] : 0.0;
-  const int e = exponent_of_max(rowmax[row]);
-  split::i8::intx4 sig[S];
-  digits16_i8<S>(v, e, sig);
-  split::i8::intx4 *dst = Apk + (blk * S) * 64 + lane;
-#pragma unroll
-  for (int s = 0; s < S; ++s) dst[s * 64] = sig[s];
-}
-
+// INT8 B slices: as k_slice_b with 32-k chunks of INT8 digits.
 template <int S>
 __global__ __launch_bounds__(256) void k_slice_b_i8(const double *__restrict__ B, int64_t K, int64_t N,
                                                     const uint64_t *__restrict__ colmax, int64_t KB, int64_t nchunks,
@@ -227,8 +235,8 @@ hipError_t launch_prepare_i8(const SplitPlan &p, const double *A, const double *
   const int64_t KB = p.Kp / 32;
   launch_scans(p, A, B, rowmax, colmax, s);
   const int64_t cha = (p.Mp / 32) * KB, chb = (p.Np / 32) * KB;
-  hipLaunchKernelGGL((k_slice_a_i8<S>), dim3((unsigned)((cha + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, KB,
-                     cha, Apk);
+  hipLaunchKernelGGL((k_slice_a<S, true>), dim3((unsigned)((cha + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax,
+                     KB, cha, Apk);
   hipLaunchKernelGGL((k_slice_b_i8<S>), dim3((unsigned)((chb + 3) / 4)), dim3(256), 0, s, B, p.K, p.N, colmax, KB,
                      chb, Bpk);
   return hipGetLastError();
@@ -259,8 +267,8 @@ hipError_t launch_prepare_s(const SplitPlan &p, const double *A, const double *B
   const int64_t KB = p.Kp / 16;
   launch_scans(p, A, B, rowmax, colmax, s);
   const int64_t cha = (p.Mp / 32) * KB, chb = (p.Np / 32) * KB;
-  hipLaunchKernelGGL((k_slice_a<S>), dim3((unsigned)((cha + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, KB, cha,
-                     Apk);
+  hipLaunchKernelGGL((k_slice_a<S, false>), dim3((unsigned)((cha + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, KB,
+                     cha, Apk);
   hipLaunchKernelGGL((k_slice_b<S>), dim3((unsigned)((chb + 3) / 4)), dim3(256), 0, s, B, p.K, p.N, colmax, KB, chb,
                      Bpk);
   return hipGetLastError();
