@@ -39,7 +39,14 @@ struct Mfma16<float> {
 // SKIP: a wave issues no MFMA for its 16 x 16 blocks that lie wholly past
 // M or N (small problems in a fixed tile: the matrix-core work then follows
 // the problem's extents in steps of 16 instead of the tile's).
-template <typename T, bool TA, bool TB, int WBM, int WBN, int BK = 16, bool GEN = false, bool SKIP = false>
+// VEC: panels are loaded as 16-byte vectors along each operand's contiguous
+// axis (4 FP32 or 2 FP64 per load: fewer load instructions and address
+// registers). The caller guarantees 16-byte aligned A and B and contiguous
+// extents that are multiples of the vector length (K for A, N for B, or M and
+// K when transposed), so a vector is either wholly inside the operand or
+// wholly past its edge. Not combined with GEN.
+template <typename T, bool TA, bool TB, int WBM, int WBN, int BK = 16, bool GEN = false, bool SKIP = false,
+          bool VEC = false>
 __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
                                           int64_t M, int64_t K, int64_t N, int64_t m0, int64_t n0, int64_t Qa = 1,
                                           int64_t Qb = 1) {
@@ -48,6 +55,9 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
   constexpr int BM = 32 * WBM, BN = 32 * WBN;
   constexpr int PAD = 2;
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  static_assert(!(VEC && GEN), "vector panels read plain layouts only");
+  constexpr int V = VEC ? 16 / (int)sizeof(T) : 1;  // elements per load
+  typedef __attribute__((__vector_size__(V * sizeof(T)))) T vec_t;
   __shared__ T As[BK][BM + PAD];
   __shared__ T Bs[BK][BN + PAD];
 
@@ -69,7 +79,7 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
 
-  T ra[EA], rb[EB];
+  vec_t ra[EA / V], rb[EB / V];
   // GEN: the row/column part of each loaded element's address is the same for
   // every k panel; -1 marks a row or column past the edge.
   [[maybe_unused]] int64_t abase[GEN ? EA : 1], bbase[GEN ? EB : 1];
@@ -87,58 +97,77 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
       bbase[e] = gn < N ? (gn / Qb) * K * Qb + gn % Qb : -1;
     }
   }
+  // Panel element f (vector f when VEC) of a thread: A runs along k unless TA
+  // (then along i), B along j unless TB (then along k), so that neighbouring
+  // lanes read neighbouring addresses.
   auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {
+    for (int e = 0; e < EA / V; ++e) {
       const int f = tid + 256 * e;
       int64_t gm, gk;
       if constexpr (!TA) {
-        gm = m0 + f / BK;
-        gk = k0 + f % BK;
+        gm = m0 + f / (BK / V);
+        gk = k0 + (f % (BK / V)) * V;
       } else {
-        gk = k0 + f / BM;
-        gm = m0 + f % BM;
+        gk = k0 + f / (BM / V);
+        gm = m0 + (f % (BM / V)) * V;
       }
       const bool ok = gm < M && gk < K;
-      if constexpr (GEN)
-        ra[e] = (abase[e] >= 0 && gk < K) ? A[abase[e] + gk * Qa] : T(0);
-      else
-        ra[e] = ok ? (TA ? A[gk * M + gm] : A[gm * K + gk]) : T(0);
+      if constexpr (GEN) {
+        ra[e][0] = (abase[e] >= 0 && gk < K) ? A[abase[e] + gk * Qa] : T(0);
+      } else {
+        const T *src = TA ? A + gk * M + gm : A + gm * K + gk;
+        if constexpr (VEC)
+          ra[e] = ok ? *(const vec_t *)src : vec_t{};
+        else
+          ra[e][0] = ok ? *src : T(0);
+      }
     }
 #pragma unroll
-    for (int e = 0; e < EB; ++e) {
+    for (int e = 0; e < EB / V; ++e) {
       const int f = tid + 256 * e;
       int64_t gn, gk;
       if constexpr (!TB) {
-        gk = k0 + f / BN;
-        gn = n0 + f % BN;
+        gk = k0 + f / (BN / V);
+        gn = n0 + (f % (BN / V)) * V;
       } else {
-        gn = n0 + f / BK;
-        gk = k0 + f % BK;
+        gn = n0 + f / (BK / V);
+        gk = k0 + (f % (BK / V)) * V;
       }
       const bool ok = gn < N && gk < K;
-      if constexpr (GEN)
-        rb[e] = (bbase[e] >= 0 && gk < K) ? B[bbase[e] + gk * Qb] : T(0);
-      else
-        rb[e] = ok ? (TB ? B[gn * K + gk] : B[gk * N + gn]) : T(0);
+      if constexpr (GEN) {
+        rb[e][0] = (bbase[e] >= 0 && gk < K) ? B[bbase[e] + gk * Qb] : T(0);
+      } else {
+        const T *src = TB ? B + gn * K + gk : B + gk * N + gn;
+        if constexpr (VEC)
+          rb[e] = ok ? *(const vec_t *)src : vec_t{};
+        else
+          rb[e][0] = ok ? *src : T(0);
+      }
     }
   };
   auto store = [&]() {
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {
+    for (int e = 0; e < EA / V; ++e) {
       const int f = tid + 256 * e;
-      if constexpr (!TA)
-        As[f % BK][f / BK] = ra[e];
-      else
-        As[f / BM][f % BM] = ra[e];
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        if constexpr (!TA)
+          As[(f % (BK / V)) * V + u][f / (BK / V)] = ra[e][u];
+        else
+          As[f / (BM / V)][(f % (BM / V)) * V + u] = ra[e][u];
+      }
     }
 #pragma unroll
-    for (int e = 0; e < EB; ++e) {
+    for (int e = 0; e < EB / V; ++e) {
       const int f = tid + 256 * e;
-      if constexpr (!TB)
-        Bs[f / BN][f % BN] = rb[e];
-      else
-        Bs[f % BK][f / BK] = rb[e];
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        if constexpr (!TB)
+          Bs[f / (BN / V)][(f % (BN / V)) * V + u] = rb[e][u];
+        else
+          Bs[(f % (BK / V)) * V + u][f / (BK / V)] = rb[e][u];
+      }
     }
   };
 

@@ -10,7 +10,9 @@
 // FP32) are staged in LDS (k-major, so one fragment read is 16 contiguous
 // elements per k row);
 // the next panel is fetched into registers while the current one is
-// multiplied. trans_a / trans_b read A stored K x M or B stored N x K, which
+// multiplied, as 16-byte vectors when the operands are aligned and their
+// contiguous extents are multiples of the vector length (VEC).
+// trans_a / trans_b read A stored K x M or B stored N x K, which
 // is how the backward pass contracts over permuted axes without a transposed
 // copy; the GEN variants read the strided (P, K, Q) views of a contraction
 // over any axis pair.
@@ -20,7 +22,7 @@
 
 namespace moa {
 
-template <typename T, bool TA, bool TB, int WBM, int WBN, bool GEN>
+template <typename T, bool TA, bool TB, int WBM, int WBN, bool GEN, bool VEC>
 __global__ __launch_bounds__(256, 2) void k_gemm(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
                                                   int64_t M, int64_t K, int64_t N, int64_t tiles_m, int64_t tiles_n,
                                                   int64_t Qa, int64_t Qb) {
@@ -28,10 +30,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const T *__restrict__ A, const 
   grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
   // FP32 MFMAs run at twice the FP64 rate: 32-wide k panels halve the
   // barriers and panel stores per flop.
-  gemm_tile<T, TA, TB, WBM, WBN, sizeof(T) == 4 ? 32 : 16, GEN>(A, B, D, M, K, N, tm * 32 * WBM, tn * 32 * WBN, Qa, Qb);
+  gemm_tile<T, TA, TB, WBM, WBN, sizeof(T) == 4 ? 32 : 16, GEN, false, VEC>(A, B, D, M, K, N, tm * 32 * WBM,
+                                                                             tn * 32 * WBN, Qa, Qb);
 }
 
-template <typename T, bool TA, bool TB, bool GEN>
+template <typename T, bool TA, bool TB, bool GEN, bool VEC>
 static hipError_t launch_t(const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile, int64_t Qa,
                            int64_t Qb, hipStream_t s) {
   if (tile == 0) {
@@ -44,29 +47,46 @@ static hipError_t launch_t(const T *A, const T *B, T *D, int64_t M, int64_t K, i
   if (tile == 3) {
     const int64_t tmn = (M + 31) / 32, tnn = (N + 31) / 32;
     if (tmn * tnn > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_gemm<T, TA, TB, 1, 1, GEN>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K,
+    hipLaunchKernelGGL((k_gemm<T, TA, TB, 1, 1, GEN, VEC>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K,
                        N, tmn, tnn, Qa, Qb);
   } else if (tile == 1) {
     const int64_t tmn = (M + 127) / 128, tnn = (N + 127) / 128;
     if (tmn * tnn > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_gemm<T, TA, TB, 4, 4, GEN>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K,
+    hipLaunchKernelGGL((k_gemm<T, TA, TB, 4, 4, GEN, VEC>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K,
                        N, tmn, tnn, Qa, Qb);
   } else {
     const int64_t tmn = (M + 63) / 64, tnn = (N + 63) / 64;
     if (tmn * tnn > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_gemm<T, TA, TB, 2, 2, GEN>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K,
+    hipLaunchKernelGGL((k_gemm<T, TA, TB, 2, 2, GEN, VEC>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K,
                        N, tmn, tnn, Qa, Qb);
   }
   return hipGetLastError();
 }
 
+template <typename T, bool GEN, bool VEC>
+static hipError_t launch_tv(bool ta, bool tb, const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile,
+                            int64_t Qa, int64_t Qb, hipStream_t s) {
+  if (!ta && !tb) return launch_t<T, false, false, GEN, VEC>(A, B, D, M, K, N, tile, Qa, Qb, s);
+  if (ta && !tb) return launch_t<T, true, false, GEN, VEC>(A, B, D, M, K, N, tile, Qa, Qb, s);
+  if (!ta && tb) return launch_t<T, false, true, GEN, VEC>(A, B, D, M, K, N, tile, Qa, Qb, s);
+  return launch_t<T, true, true, GEN, VEC>(A, B, D, M, K, N, tile, Qa, Qb, s);
+}
+
+// Vector panels need 16-byte aligned operands whose contiguous extents (the
+// row length of A and of B as stored) are multiples of the vector length.
+template <typename T>
+static bool vec_ok(bool ta, bool tb, const T *A, const T *B, int64_t M, int64_t K, int64_t N) {
+  constexpr int64_t V = 16 / sizeof(T);
+  const int64_t a_row = ta ? M : K, b_row = tb ? K : N;
+  return ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0 && a_row % V == 0 && b_row % V == 0;
+}
+
 template <typename T, bool GEN>
 static hipError_t launch_tt(bool ta, bool tb, const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile,
                             int64_t Qa, int64_t Qb, hipStream_t s) {
-  if (!ta && !tb) return launch_t<T, false, false, GEN>(A, B, D, M, K, N, tile, Qa, Qb, s);
-  if (ta && !tb) return launch_t<T, true, false, GEN>(A, B, D, M, K, N, tile, Qa, Qb, s);
-  if (!ta && tb) return launch_t<T, false, true, GEN>(A, B, D, M, K, N, tile, Qa, Qb, s);
-  return launch_t<T, true, true, GEN>(A, B, D, M, K, N, tile, Qa, Qb, s);
+  if constexpr (!GEN)
+    if (vec_ok(ta, tb, A, B, M, K, N)) return launch_tv<T, false, true>(ta, tb, A, B, D, M, K, N, tile, Qa, Qb, s);
+  return launch_tv<T, GEN, false>(ta, tb, A, B, D, M, K, N, tile, Qa, Qb, s);
 }
 
 hipError_t launch_gemm(moa_dtype dt, bool trans_a, bool trans_b, const void *A, const void *B, void *D, int64_t M,

@@ -233,6 +233,28 @@ def test_mfma_plus_times(dt, tol):
         assert nerr(d, ref) <= tol, nerr(d, ref)
 
 
+@pytest.mark.parametrize("dt,tol", [(np.float64, 1e-13), (np.float32, 1e-5)])
+def test_mfma_vector_panels_ragged_and_misaligned(dt, tol):
+    # Contiguous extents that are multiples of 4 take the 16-byte vector panel
+    # loads; ragged M and N exercise their edges. The same operands at an
+    # address 1 element past a 16-byte boundary must take the scalar loads.
+    rng = np.random.default_rng(109)
+    for sa, sb in [((257, 132), (132, 516)), ((3, 45, 64), (64, 6, 10)), ((1030, 68), (68, 36))]:
+        a = mi.uniform_f64(rng, sa).astype(dt)
+        b = mi.uniform_f64(rng, sb).astype(dt)
+        ref = oracle.inner_dot2(a, b)
+        say("mfma vector panels", np.dtype(dt).name, sa, sb)
+        assert nerr(host(moa.inner(gpu(a), gpu(b))), ref) <= tol
+        ta = torch.zeros(a.size + 1, dtype=gpu(a).dtype, device=DEV)
+        tb = torch.zeros(b.size + 1, dtype=gpu(b).dtype, device=DEV)
+        ta[1:] = gpu(a.ravel())
+        tb[1:] = gpu(b.ravel())
+        av, bv = ta[1:].view(sa), tb[1:].view(sb)
+        assert av.data_ptr() % 16 != 0 and bv.data_ptr() % 16 != 0
+        say("mfma misaligned", np.dtype(dt).name, sa, sb)
+        assert nerr(host(moa.inner(av, bv)), ref) <= tol
+
+
 def test_mfma_f64_exact_integers():
     # Integer entries with |x| <= 8 and K <= 8192: every partial sum is exact,
     # so any summation order gives the exact product.
