@@ -39,12 +39,13 @@ struct Mfma16<float> {
 // SKIP: a wave issues no MFMA for its 16 x 16 blocks that lie wholly past
 // M or N (small problems in a fixed tile: the matrix-core work then follows
 // the problem's extents in steps of 16 instead of the tile's).
-// VEC: panels are loaded as 16-byte vectors along each operand's contiguous
-// axis (4 FP32 or 2 FP64 per load: fewer load instructions and address
-// registers). The caller guarantees 16-byte aligned A and B and contiguous
-// extents that are multiples of the vector length (K for A, N for B, or M and
-// K when transposed), so a vector is either wholly inside the operand or
-// wholly past its edge. Not combined with GEN.
+// VEC: panels are loaded as 16-byte vectors along the axis the lanes run on
+// (4 FP32 or 2 FP64 per load: fewer load instructions and address
+// registers). The caller guarantees 16-byte aligned A and B and extents along
+// those axes that are multiples of the vector length (K for A, N for B, or M
+// and K when transposed; with GEN, Qa and Qb wherever the lanes run along i
+// or j), so a vector is either wholly inside the operand or wholly past its
+// edge and its elements are adjacent in memory.
 template <typename T, bool TA, bool TB, int WBM, int WBN, int BK = 16, bool GEN = false, bool SKIP = false,
           bool VEC = false>
 __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
@@ -55,7 +56,6 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
   constexpr int BM = 32 * WBM, BN = 32 * WBN;
   constexpr int PAD = 2;
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
-  static_assert(!(VEC && GEN), "vector panels read plain layouts only");
   constexpr int V = VEC ? 16 / (int)sizeof(T) : 1;  // elements per load
   typedef __attribute__((__vector_size__(V * sizeof(T)))) T vec_t;
   __shared__ T As[BK][BM + PAD];
@@ -82,18 +82,18 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
   vec_t ra[EA / V], rb[EB / V];
   // GEN: the row/column part of each loaded element's address is the same for
   // every k panel; -1 marks a row or column past the edge.
-  [[maybe_unused]] int64_t abase[GEN ? EA : 1], bbase[GEN ? EB : 1];
+  [[maybe_unused]] int64_t abase[GEN ? EA / V : 1], bbase[GEN ? EB / V : 1];
   if constexpr (GEN) {
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {
+    for (int e = 0; e < EA / V; ++e) {
       const int f = tid + 256 * e;
-      const int64_t gm = m0 + (TA ? f % BM : f / BK);
+      const int64_t gm = m0 + (TA ? (f % (BM / V)) * V : f / (BK / V));
       abase[e] = gm < M ? (gm / Qa) * K * Qa + gm % Qa : -1;
     }
 #pragma unroll
-    for (int e = 0; e < EB; ++e) {
+    for (int e = 0; e < EB / V; ++e) {
       const int f = tid + 256 * e;
-      const int64_t gn = n0 + (TB ? f / BK : f % BN);
+      const int64_t gn = n0 + (TB ? f / (BK / V) : (f % (BN / V)) * V);
       bbase[e] = gn < N ? (gn / Qb) * K * Qb + gn % Qb : -1;
     }
   }
@@ -114,7 +114,11 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
       }
       const bool ok = gm < M && gk < K;
       if constexpr (GEN) {
-        ra[e][0] = (abase[e] >= 0 && gk < K) ? A[abase[e] + gk * Qa] : T(0);
+        const bool in = abase[e] >= 0 && gk < K;
+        if constexpr (VEC)
+          ra[e] = in ? *(const vec_t *)(A + abase[e] + gk * Qa) : vec_t{};
+        else
+          ra[e][0] = in ? A[abase[e] + gk * Qa] : T(0);
       } else {
         const T *src = TA ? A + gk * M + gm : A + gm * K + gk;
         if constexpr (VEC)
@@ -136,7 +140,11 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
       }
       const bool ok = gn < N && gk < K;
       if constexpr (GEN) {
-        rb[e][0] = (bbase[e] >= 0 && gk < K) ? B[bbase[e] + gk * Qb] : T(0);
+        const bool in = bbase[e] >= 0 && gk < K;
+        if constexpr (VEC)
+          rb[e] = in ? *(const vec_t *)(B + bbase[e] + gk * Qb) : vec_t{};
+        else
+          rb[e][0] = in ? B[bbase[e] + gk * Qb] : T(0);
       } else {
         const T *src = TB ? B + gn * K + gk : B + gk * N + gn;
         if constexpr (VEC)

@@ -72,32 +72,37 @@ static hipError_t launch_tv(bool ta, bool tb, const T *A, const T *B, T *D, int6
   return launch_t<T, true, true, GEN, VEC>(A, B, D, M, K, N, tile, Qa, Qb, s);
 }
 
-// Vector panels need 16-byte aligned operands whose contiguous extents (the
-// row length of A and of B as stored) are multiples of the vector length.
+// Vector panels need 16-byte aligned operands whose extents along the lanes'
+// axis are multiples of the vector length: the stored row length of A and B,
+// or for the strided views the inner extent Qa (Qb) when it is not 1 and K
+// when it is.
 template <typename T>
-static bool vec_ok(bool ta, bool tb, const T *A, const T *B, int64_t M, int64_t K, int64_t N) {
+static bool vec_ok(const T *A, const T *B, int64_t a_run, int64_t b_run) {
   constexpr int64_t V = 16 / sizeof(T);
-  const int64_t a_row = ta ? M : K, b_row = tb ? K : N;
-  return ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0 && a_row % V == 0 && b_row % V == 0;
+  return ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0 && a_run % V == 0 && b_run % V == 0;
 }
 
 template <typename T, bool GEN>
-static hipError_t launch_tt(bool ta, bool tb, const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile,
-                            int64_t Qa, int64_t Qb, hipStream_t s) {
-  if constexpr (!GEN)
-    if (vec_ok(ta, tb, A, B, M, K, N)) return launch_tv<T, false, true>(ta, tb, A, B, D, M, K, N, tile, Qa, Qb, s);
+static hipError_t launch_tt(bool ta, bool tb, bool vec, const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N,
+                            int tile, int64_t Qa, int64_t Qb, hipStream_t s) {
+  if (vec) return launch_tv<T, GEN, true>(ta, tb, A, B, D, M, K, N, tile, Qa, Qb, s);
   return launch_tv<T, GEN, false>(ta, tb, A, B, D, M, K, N, tile, Qa, Qb, s);
 }
 
 hipError_t launch_gemm(moa_dtype dt, bool trans_a, bool trans_b, const void *A, const void *B, void *D, int64_t M,
                        int64_t K, int64_t N, int tile, hipStream_t s) {
   if (M == 0 || N == 0) return hipSuccess;
-  if (dt == MOA_F64)
-    return launch_tt<double, false>(trans_a, trans_b, (const double *)A, (const double *)B, (double *)D, M, K, N, tile,
-                                    1, 1, s);
-  if (dt == MOA_F32)
-    return launch_tt<float, false>(trans_a, trans_b, (const float *)A, (const float *)B, (float *)D, M, K, N, tile, 1,
-                                   1, s);
+  const int64_t a_run = trans_a ? M : K, b_run = trans_b ? K : N;
+  if (dt == MOA_F64) {
+    const double *a = (const double *)A, *b = (const double *)B;
+    return launch_tt<double, false>(trans_a, trans_b, vec_ok(a, b, a_run, b_run), a, b, (double *)D, M, K, N, tile, 1,
+                                    1, s);
+  }
+  if (dt == MOA_F32) {
+    const float *a = (const float *)A, *b = (const float *)B;
+    return launch_tt<float, false>(trans_a, trans_b, vec_ok(a, b, a_run, b_run), a, b, (float *)D, M, K, N, tile, 1, 1,
+                                   s);
+  }
   return hipErrorInvalidValue;
 }
 
@@ -109,10 +114,15 @@ hipError_t launch_gemm_strided(moa_dtype dt, const void *A, const void *B, void 
   if (M == 0 || N == 0) return hipSuccess;
   if (Qa <= 0 || Qb <= 0) return hipErrorInvalidValue;
   const bool ta = Qa != 1, tb = Qb == 1;
-  if (dt == MOA_F64)
-    return launch_tt<double, true>(ta, tb, (const double *)A, (const double *)B, (double *)D, M, K, N, 0, Qa, Qb, s);
-  if (dt == MOA_F32)
-    return launch_tt<float, true>(ta, tb, (const float *)A, (const float *)B, (float *)D, M, K, N, 0, Qa, Qb, s);
+  const int64_t a_run = ta ? Qa : K, b_run = tb ? K : Qb;
+  if (dt == MOA_F64) {
+    const double *a = (const double *)A, *b = (const double *)B;
+    return launch_tt<double, true>(ta, tb, vec_ok(a, b, a_run, b_run), a, b, (double *)D, M, K, N, 0, Qa, Qb, s);
+  }
+  if (dt == MOA_F32) {
+    const float *a = (const float *)A, *b = (const float *)B;
+    return launch_tt<float, true>(ta, tb, vec_ok(a, b, a_run, b_run), a, b, (float *)D, M, K, N, 0, Qa, Qb, s);
+  }
   return hipErrorInvalidValue;
 }
 

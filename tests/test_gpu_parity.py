@@ -551,6 +551,8 @@ AXES_CASES = [
     ((3, 70, 2, 5), 1, (70, 140), 0),      # A strided, B plain
     ((90, 37), 1, (11, 37, 12), 1),        # A plain, B strided
     ((17, 130), 0, (17,), 0),              # A stored K x M, vector result
+    ((5, 36, 8), 1, (12, 36, 20), 1),      # inner extents multiples of 4: vector panels, strided
+    ((9, 40, 4), 1, (7, 40), 1),           # A strided (Qa = 4), B stored N x K (K = 40)
 ]
 
 
