@@ -7,14 +7,15 @@
 // With few columns the row form (a row of B per element of A) leaves most
 // lanes of a wave idle, so here the lanes share the fold over l instead. A
 // workgroup owns 4 R rows of D (R per wave) and walks l in chunks of 256: the
-// chunk's rows of B (256 N contiguous elements) are staged once in LDS, lane q
-// of a wave folds l = q, q + 64, q + 128, q + 192 of the chunk for its R rows
-// and all N columns (every A load is 64 consecutive elements of a row, so A,
-// the stream that dominates, is read once and coalesced), and after the last
-// chunk the 64 partial folds of each element are combined by a butterfly of
-// cross-lane exchanges. The combination order differs from a sequential fold,
-// so this path is used only for folds whose result does not depend on
-// association: every int32 fold (wrapping + and * included) and FP max/min.
+// chunk's rows of B (256 N contiguous elements) are staged once in LDS, and
+// within each span of 64 VW consecutive l (VW = elements per 16 bytes) lane q
+// folds l = VW q .. VW q + VW - 1 for its R rows and all N columns, so every
+// A load is one 16-byte vector per lane and 1 KiB per wave (A, the stream that
+// dominates, is read once and coalesced). After the last chunk the 64 partial
+// folds of each element are combined by a butterfly of cross-lane exchanges.
+// The combination order differs from a sequential fold, so this path is used
+// only for folds whose result does not depend on association: every int32
+// fold (wrapping + and * included) and FP max/min.
 #pragma clang fp contract(off)
 
 #include "common.hpp"
@@ -24,13 +25,19 @@ namespace moa {
 
 namespace {
 
-constexpr int kChunk = 256;  // l per chunk: 4 per lane
+constexpr int kChunk = 256;  // l per chunk
 
+// vec: A is 16-byte aligned and K is a multiple of VW, so a lane's VW values
+// are one aligned vector; otherwise they are loaded one by one.
 template <typename T, int OP1, int OP2, int NC, int R>
 __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
-                                                 int64_t M, int64_t K, int N) {
-  // Row stride of the staged B chunk: odd (NC + 1 words or double words), so
-  // the 64 lanes reading 64 consecutive rows at one column hit distinct banks.
+                                                 int64_t M, int64_t K, int N, int vec) {
+  constexpr int VW = 16 / (int)sizeof(T), SPAN = kWave * VW, NSPAN = kChunk / SPAN;
+  typedef __attribute__((__vector_size__(16))) T vec_t;
+  // Row l of a chunk sits at LDS row (l / SPAN) SPAN + (l % VW) 64 + (l % SPAN) / VW,
+  // so the 64 lanes reading their u-th values of one column read 64 rows in a
+  // row; the row stride is odd (NC + 1 words or double words), so those reads
+  // hit distinct banks.
   constexpr int SB = NC == 1 ? 1 : NC + 1;
   __shared__ T Bs[kChunk * SB];
   const int tid = threadIdx.x, lane = tid % kWave;
@@ -52,52 +59,74 @@ __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const 
   for (int64_t k0 = 0; k0 < K; k0 += kChunk) {
     const int kc = (K - k0) < kChunk ? (int)(K - k0) : kChunk;
     // Stage rows k0 .. k0 + kc - 1 of B (one contiguous block of kc N):
-    // thread t takes column t % NP of rows t / NP, t / NP + 256 / NP, ...
-    // (NP = NC rounded up to a power of two, so no division by N).
+    // thread t takes column t % NP of rows t / NP + j 256 / NP (NP = NC
+    // rounded up to a power of two, so no division by N). When N = NP and the
+    // chunk is full that is element t + 256 j of the block: the loads are
+    // unrolled with constant offsets and all issued before the first store.
     __syncthreads();
     {
       constexpr int NP = NC <= 1 ? 1 : NC <= 2 ? 2 : NC <= 4 ? 4 : NC <= 8 ? 8 : 16;
+      constexpr int RPT = kChunk * NP / 256;  // rows per thread
       const int c = tid % NP;
-      if (c < N)
-        for (int r = tid / NP; r < kc; r += 256 / NP) Bs[r * SB + c] = B[(k0 + r) * N + c];
+      auto pos = [](int l) { return (l / SPAN) * SPAN + (l % VW) * kWave + (l % SPAN) / VW; };
+      if (N == NP && kc == kChunk) {
+        const T *src = B + k0 * NP + tid;
+        T bv[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) bv[j] = src[256 * j];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) Bs[pos(tid / NP + j * (256 / NP)) * SB + c] = bv[j];
+      } else if (c < N) {
+        for (int l = tid / NP; l < kc; l += 256 / NP) Bs[pos(l) * SB + c] = B[(k0 + l) * N + c];
+      }
     }
     __syncthreads();
-    // Lane q folds l = q, q + 64, q + 128, q + 192 of the chunk: each load of
-    // an A row is 64 consecutive elements across the wave.
-    if (kc == kChunk) {
-      T x[R][4];
 #pragma unroll
-      for (int r = 0; r < R; ++r)
+    for (int h = 0; h < NSPAN; ++h) {
+      const int l0 = h * SPAN + VW * lane;  // this lane's first l in the chunk
+      if (kc == kChunk) {
+        T x[R][VW];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) x[r][u] = a[r][k0 + lane + kWave * u];
+        for (int r = 0; r < R; ++r) {
+          if (vec) {
+            const vec_t v = *(const vec_t *)(a[r] + k0 + l0);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        if (c < N) {
-          const T b0 = Bs[lane * SB + c], b1 = Bs[(lane + kWave) * SB + c];
-          const T b2 = Bs[(lane + 2 * kWave) * SB + c], b3 = Bs[(lane + 3 * kWave) * SB + c];
+            for (int u = 0; u < VW; ++u) x[r][u] = v[u];
+          } else {
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            // Pairs of terms (three-operand fold for int32).
-            acc[r][c] = fold_pair<OP1>(acc[r][c], apply_op<OP2>(x[r][0], b0), apply_op<OP2>(x[r][1], b1));
-            acc[r][c] = fold_pair<OP1>(acc[r][c], apply_op<OP2>(x[r][2], b2), apply_op<OP2>(x[r][3], b3));
+            for (int u = 0; u < VW; ++u) x[r][u] = a[r][k0 + l0 + u];
           }
         }
-      }
-    } else {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int l = lane + kWave * u;
-        if (l < kc) {
-          T x[R];
+        for (int c = 0; c < NC; ++c) {
+          if (c < N) {
+            T b[VW];
 #pragma unroll
-          for (int r = 0; r < R; ++r) x[r] = a[r][k0 + l];
+            for (int u = 0; u < VW; ++u) b[u] = Bs[(h * SPAN + u * kWave + lane) * SB + c];
 #pragma unroll
-          for (int c = 0; c < NC; ++c)
-            if (c < N) {
-              const T bv = Bs[l * SB + c];
+            for (int r = 0; r < R; ++r)
 #pragma unroll
-              for (int r = 0; r < R; ++r) acc[r][c] = apply_op<OP1>(acc[r][c], apply_op<OP2>(x[r], bv));
-            }
+              for (int u = 0; u < VW; u += 2)  // pairs of terms (three-operand fold for int32)
+                acc[r][c] = fold_pair<OP1>(acc[r][c], apply_op<OP2>(x[r][u], b[u]),
+                                           apply_op<OP2>(x[r][u + 1], b[u + 1]));
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < VW; ++u) {
+          const int l = l0 + u;
+          if (l < kc) {
+            T x[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[r] = a[r][k0 + l];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+              if (c < N) {
+                const T bv = Bs[(h * SPAN + u * kWave + lane) * SB + c];
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r][c] = apply_op<OP1>(acc[r][c], apply_op<OP2>(x[r], bv));
+              }
+          }
         }
       }
     }
@@ -118,19 +147,21 @@ __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const 
   }
 }
 
-// Rows per wave (each staged B element feeds R terms): 4 measured best on
-// int32 (max,+) 65536 x 4096 . 4096 x 8 (0.346 ms; 2 rows: 0.378, 8: 0.434).
+// Rows per wave (each staged B element feeds R terms): 2, measured on int32
+// (max,+) 65536 x 4096 . 4096 x 8 (0.220 ms; 4 rows: 0.223 ms with twice the
+// registers).
 template <typename T, int NC>
 constexpr int rows_per_wave() {
-  return (sizeof(T) == 8 && NC > 8) ? 2 : 4;
+  return 2;
 }
 
 template <typename T, int OP1, int OP2, int NC>
 void launch_ncr(const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, hipStream_t s) {
   constexpr int R = rows_per_wave<T, NC>();
   const int64_t blocks = (M + 4 * R - 1) / (4 * R);
+  const int vec = ((uintptr_t)A % 16) == 0 && K % (16 / (int64_t)sizeof(T)) == 0;
   hipLaunchKernelGGL((k_fewcols<T, OP1, OP2, NC, R>), dim3((unsigned)blocks), dim3(256), 0, s, A, B, D, M, K,
-                     (int)N);
+                     (int)N, vec);
 }
 
 template <typename T, int OP1, int OP2>

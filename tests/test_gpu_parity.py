@@ -174,6 +174,23 @@ def test_few_columns_wave_reduction_bit_exact(dt):
                 eq(host(moa.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
 
 
+@pytest.mark.parametrize("dt", [np.int32, np.float64])
+def test_few_columns_misaligned_rows(dt):
+    # A one element past a 16-byte boundary: the per-element loads instead of
+    # the vector loads, same results.
+    rng = np.random.default_rng(113)
+    M, K, N = 70, 1000, 5
+    a = rand(rng, (M, K), dt)
+    b = rand(rng, (K, N), dt)
+    ta = torch.zeros(a.size + 1, dtype=gpu(a).dtype, device=DEV)
+    ta[1:] = gpu(a.ravel())
+    av = ta[1:].view(M, K)
+    assert av.data_ptr() % 16 != 0
+    op1 = "xor" if dt == np.int32 else "max"
+    say("few columns misaligned", np.dtype(dt).name, op1)
+    eq(host(moa.inner(av, gpu(b), op1, "add")), oracle.inner(a, b, op1, "add", mode="native"))
+
+
 def test_few_columns_workload_sampled():
     # int32 (max,+) <65536 4096> . <4096 8>: rows checked against the oracle.
     a, b = mi.workload_fewcols()
