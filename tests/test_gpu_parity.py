@@ -121,6 +121,26 @@ def test_simt_tiles_and_tails(tile):
     eq(host(moa.inner(gpu(af), gpu(bf), "add", "sub")), oracle.inner(af, bf, "add", "sub", mode="native"))
 
 
+@pytest.mark.parametrize("dt", [np.int32, np.float64, np.float32])
+def test_simt_vector_staging_ragged_and_misaligned(dt):
+    # K and N multiples of 4: 16-byte staging loads, ragged M and N edges;
+    # the same operands one element past a 16-byte boundary: scalar loads.
+    rng = np.random.default_rng(114)
+    pairs = [("max", "add"), ("min", "sub")] + ([("xor", "and")] if dt == np.int32 else [("add", "mul")])
+    for M, K, N in [(300, 40, 260), (1030, 64, 200), (70, 36, 4)]:
+        a = rand(rng, (M, K), dt)
+        b = rand(rng, (K, N), dt)
+        ta = torch.zeros(a.size + 1, dtype=gpu(a).dtype, device=DEV)
+        ta[1:] = gpu(a.ravel())
+        av = ta[1:].view(M, K)
+        assert av.data_ptr() % 16 != 0
+        for op1, op2 in pairs:
+            ref = oracle.inner(a, b, op1, op2, mode="native")
+            for name, ga in (("aligned", gpu(a)), ("misaligned", av)):
+                say("simt staging", name, np.dtype(dt).name, M, K, N, op1, op2)
+                eq(host(moa.inner_ex(ga, gpu(b), op1, op2, flags=moa.FLAG_SEQUENTIAL_FOLD)), ref)
+
+
 @pytest.mark.parametrize("dt", [np.float64, np.float32, np.int32])
 def test_few_rows_stream_all_pairs_bit_exact(dt):
     # At most 8 result rows and >= 4096 columns: the row-form stream kernel,
