@@ -4,7 +4,8 @@
 // store stream (one IEEE op per element, so results are bit-exact): each thread
 // holds a 16-byte slice of B in registers for the whole launch and writes it
 // combined with one element of A per row, so every row of C is written as
-// contiguous 16-byte non-temporal stores and A and B are read once.
+// contiguous 16-byte stores and A and B are read once. (Non-temporal stores
+// measured 4% slower on FP32 <512 512> o <64 64>: 0.735 vs 0.708 ms.)
 #pragma clang fp contract(off)
 
 #include "common.hpp"
@@ -34,7 +35,7 @@ __global__ __launch_bounds__(256) void k_outer_vec(const T *__restrict__ A, cons
     V out;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) out[e] = apply_op<OP>(a, b[e]);
-    __builtin_nontemporal_store(out, (V *)(C + r * NB + j0));
+    *(V *)(C + r * NB + j0) = out;
   }
 }
 
