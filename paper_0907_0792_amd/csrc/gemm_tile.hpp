@@ -46,11 +46,13 @@ struct Mfma16<float> {
 // and K when transposed; with GEN, Qa and Qb wherever the lanes run along i
 // or j), so a vector is either wholly inside the operand or wholly past its
 // edge and its elements are adjacent in memory.
+// I: index type. int32_t when the caller knows every offset of the tile
+// (operand and result extents padded by a tile) fits in 31 bits: 32-bit
+// address arithmetic takes fewer registers (small batched problems).
 template <typename T, bool TA, bool TB, int WBM, int WBN, int BK = 16, bool GEN = false, bool SKIP = false,
-          bool VEC = false>
+          bool VEC = false, typename I = int64_t>
 __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
-                                          int64_t M, int64_t K, int64_t N, int64_t m0, int64_t n0, int64_t Qa = 1,
-                                          int64_t Qb = 1) {
+                                          I M, I K, I N, I m0, I n0, I Qa = 1, I Qb = 1) {
   using MF = Mfma16<T>;
   using acc_t = typename MF::acc_t;
   constexpr int BM = 32 * WBM, BN = 32 * WBN;
@@ -66,7 +68,7 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
   // Blocks of this wave inside the problem (all of them unless SKIP).
   int nbm = WBM, nbn = WBN;
   if constexpr (SKIP) {
-    const int64_t rm = M - (m0 + wm * (BM / 2)), rn = N - (n0 + wn * (BN / 2));
+    const I rm = M - (m0 + wm * (BM / 2)), rn = N - (n0 + wn * (BN / 2));
     nbm = rm <= 0 ? 0 : (rm >= 16 * WBM ? WBM : (int)((rm + 15) / 16));
     nbn = rn <= 0 ? 0 : (rn >= 16 * WBN ? WBN : (int)((rn + 15) / 16));
   }
@@ -82,29 +84,29 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
   vec_t ra[EA / V], rb[EB / V];
   // GEN: the row/column part of each loaded element's address is the same for
   // every k panel; -1 marks a row or column past the edge.
-  [[maybe_unused]] int64_t abase[GEN ? EA / V : 1], bbase[GEN ? EB / V : 1];
+  [[maybe_unused]] I abase[GEN ? EA / V : 1], bbase[GEN ? EB / V : 1];
   if constexpr (GEN) {
 #pragma unroll
     for (int e = 0; e < EA / V; ++e) {
       const int f = tid + 256 * e;
-      const int64_t gm = m0 + (TA ? (f % (BM / V)) * V : f / (BK / V));
+      const I gm = m0 + (TA ? (f % (BM / V)) * V : f / (BK / V));
       abase[e] = gm < M ? (gm / Qa) * K * Qa + gm % Qa : -1;
     }
 #pragma unroll
     for (int e = 0; e < EB / V; ++e) {
       const int f = tid + 256 * e;
-      const int64_t gn = n0 + (TB ? f / (BK / V) : (f % (BN / V)) * V);
+      const I gn = n0 + (TB ? f / (BK / V) : (f % (BN / V)) * V);
       bbase[e] = gn < N ? (gn / Qb) * K * Qb + gn % Qb : -1;
     }
   }
   // Panel element f (vector f when VEC) of a thread: A runs along k unless TA
   // (then along i), B along j unless TB (then along k), so that neighbouring
   // lanes read neighbouring addresses.
-  auto load = [&](int64_t k0) {
+  auto load = [&](I k0) {
 #pragma unroll
     for (int e = 0; e < EA / V; ++e) {
       const int f = tid + 256 * e;
-      int64_t gm, gk;
+      I gm, gk;
       if constexpr (!TA) {
         gm = m0 + f / (BK / V);
         gk = k0 + (f % (BK / V)) * V;
@@ -130,7 +132,7 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
 #pragma unroll
     for (int e = 0; e < EB / V; ++e) {
       const int f = tid + 256 * e;
-      int64_t gn, gk;
+      I gn, gk;
       if constexpr (!TB) {
         gk = k0 + f / (BN / V);
         gn = n0 + (f % (BN / V)) * V;
@@ -179,9 +181,9 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
     }
   };
 
-  const int64_t nk = (K + BK - 1) / BK;
+  const I nk = (K + BK - 1) / BK;
   if (nk > 0) load(0);
-  for (int64_t kt = 0; kt < nk; ++kt) {
+  for (I kt = 0; kt < nk; ++kt) {
     __syncthreads();
     store();
     __syncthreads();
@@ -207,8 +209,8 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
     for (int j = 0; j < WBN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t gm = m0 + wm * (BM / 2) + i * 16 + MF::row(lane, v);
-        const int64_t gn = n0 + wn * (BN / 2) + j * 16 + lane % 16;
+        const I gm = m0 + wm * (BM / 2) + i * 16 + MF::row(lane, v);
+        const I gn = n0 + wn * (BN / 2) + j * 16 + lane % 16;
         if (gm < M && gn < N) D[gm * N + gn] = acc[i][j][v];
       }
 }
