@@ -538,6 +538,25 @@ def test_batch_small_full_check():
     bt.close()
 
 
+def test_batch_wide_problem_64bit_offsets():
+    # A problem whose padded extents pass 2^31 offsets makes the whole batch
+    # use 64-bit tile index arithmetic. Small integer entries: exact sums.
+    rng = np.random.default_rng(115)
+    shapes = [((2, 3), (3, 32_100_000)), ((5, 7), (7, 9)), ((40, 130), (130, 33))]
+    a_s = [rng.integers(-2, 3, size=sa).astype(np.float32) for sa, _ in shapes]
+    b_s = [rng.integers(-2, 3, size=sb).astype(np.float32) for _, sb in shapes]
+    As, Bs = [gpu(a) for a in a_s], [gpu(b) for b in b_s]
+    Ds = [torch.full((sa[0], sb[1]), float("nan"), device=DEV) for sa, sb in shapes]
+    say("batch with a 2 x 3 . 3 x 32.1M problem")
+    bt = moa.Batch(As, Bs, Ds)
+    bt.run()
+    for a, b, d in zip(a_s, b_s, Ds):
+        eq(host(d), (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float32))
+    bt.close()
+    del As, Bs, Ds
+    torch.cuda.empty_cache()
+
+
 def test_batch_full_size_sampled():
     probs = mi.batch_problems(mi.rng_for(mi.BATCH), 10000)
     As = [gpu(p.a) for p in probs]
