@@ -103,11 +103,22 @@ def _check(status: int):
         raise MoaError(status, lib().moa_last_error().decode())
 
 
+_SHAPES = {}
+
+
 def _shape(dims):
-    dims = [int(d) for d in dims]
-    arr = (ctypes.c_int64 * max(1, len(dims)))(*dims)
-    s = _Shape(len(dims), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int64)))
-    s._keep = arr  # keep the array alive with the struct
+    """moa_shape for a shape tuple. The structs are immutable once built, so
+    they are cached per shape (building one costs a few microseconds, which
+    small products notice)."""
+    key = tuple(dims)
+    s = _SHAPES.get(key)
+    if s is None:
+        ints = [int(d) for d in key]
+        arr = (ctypes.c_int64 * max(1, len(ints)))(*ints)
+        s = _Shape(len(ints), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int64)))
+        s._keep = arr  # keep the array alive with the struct
+        if len(_SHAPES) < 4096:
+            _SHAPES[key] = s
     return s
 
 
@@ -186,7 +197,8 @@ def inner_ex(a: torch.Tensor, b: torch.Tensor, op1: str = "add", op2: str = "mul
     dev = _dev_operands(a, b)
     a = a.contiguous()
     b = b.contiguous()
-    rs = inner_shape(a.shape, b.shape)
+    # Result shape rho A[:-1] ++ rho B[1:]; the library validates the operands.
+    rs = tuple(a.shape[:-1]) + tuple(b.shape[1:])
     if out is None:
         out = torch.empty(rs, dtype=a.dtype, device=dev)
     elif tuple(out.shape) != rs or out.dtype != a.dtype or not out.is_contiguous():
@@ -208,7 +220,7 @@ def outer(a: torch.Tensor, b: torch.Tensor, op: str = "mul", out: torch.Tensor |
     dev = _dev_operands(a, b)
     a = a.contiguous()
     b = b.contiguous()
-    rs = outer_shape(a.shape, b.shape)
+    rs = tuple(a.shape) + tuple(b.shape)  # rho A ++ rho B; the library validates
     if out is None:
         out = torch.empty(rs, dtype=a.dtype, device=dev)
     elif tuple(out.shape) != rs or out.dtype != a.dtype or not out.is_contiguous():
@@ -230,7 +242,8 @@ def inner_split(a: torch.Tensor, b: torch.Tensor, fmt: str = "bf16", nslices: in
     dev = _dev_operands(a, b)
     a = a.contiguous()
     b = b.contiguous()
-    rs = inner_shape(a.shape, b.shape)
+    # Result shape rho A[:-1] ++ rho B[1:]; the library validates the operands.
+    rs = tuple(a.shape[:-1]) + tuple(b.shape[1:])
     if out is None:
         out = torch.empty(rs, dtype=torch.float64, device=dev)
     nbytes = split_workspace_bytes(a.shape, b.shape, fmt, nslices)
