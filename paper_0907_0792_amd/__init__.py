@@ -173,7 +173,8 @@ def inner_axes(a: torch.Tensor, b: torch.Tensor, axes=(-1, 0), op1: str = "add",
     a = a.contiguous()
     b = b.contiguous()
     ax_a, ax_b = _axis(axes[0], a.dim()), _axis(axes[1], b.dim())
-    rs = inner_axes_shape(a.shape, ax_a, b.shape, ax_b)
+    # A's free axes, then B's; the library validates the axes and extents.
+    rs = tuple(d for i, d in enumerate(a.shape) if i != ax_a) + tuple(d for i, d in enumerate(b.shape) if i != ax_b)
     if out is None:
         out = torch.empty(rs, dtype=a.dtype, device=dev)
     elif tuple(out.shape) != rs or out.dtype != a.dtype or not out.is_contiguous():
