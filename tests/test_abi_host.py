@@ -4,6 +4,7 @@ every call here returns before touching the device)."""
 import ctypes
 import os
 import re
+import sys
 
 import numpy as np
 import pytest
@@ -219,3 +220,12 @@ def test_inner_shape_of_two_rank16_operands():
     assert got == sa[:-1] + sb[1:] and len(got) == 30
     assert moa.inner_axes_shape(sa, 15, sb, 0) == got
     assert moa.outer_shape((1,) * 16, (2,) * 16) == (1,) * 16 + (2,) * 16
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # One GPU only: --gpus N > 1 exits with a message before touching a GPU.
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
