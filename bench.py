@@ -22,7 +22,9 @@ same fields, their own roofline): plain64 (FP64 (+,*) 8192^3), rank5 (FP64
 (FP32 (-) <512 512> o <64 64>), batch (10,000 uneven FP32 products, one graph
 launch), grad (FP32 forward + backward <32 128 512>.<512 64 64>), small
 (FP64 512^3 plus the <32 32> o <16 16> outer product), skinny (the paper's
-own FP64 4 x 128 . 128 x 2^22 product, HBM-bound).
+own FP64 4 x 128 . 128 x 2^22 product, HBM-bound), axes (FP64 <16 2048 512>
+. <16 2048 512> contracted over axes (1, 1), read in place), fewcols (int32
+(max,+) 65536 x 4096 . 4096 x 8, wavefront-reduced fold).
 """
 from __future__ import annotations
 
