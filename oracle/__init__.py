@@ -11,6 +11,9 @@ Python entry points (all host NumPy, row-major):
 * :func:`inner_dot2` — compensated (+,*) FP64 reference (Ogita-Rump-Oishi Dot2).
 * :func:`split_digits`, :func:`split_inner` — the signed-digit split (Ozaki)
   scheme with exact integer slice products.
+* :func:`normwise_error`, :func:`maxnorm_error`, :func:`componentwise_error`
+  (with :func:`abs_product`) — the error measures results are judged by
+  (normwise is the gate; the other two are reported).
 * :mod:`oracle.brute` — pure-Python brute force over full index tuples.
 
 Op names: ``add sub mul div max min and or xor``.
@@ -29,10 +32,12 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "max": 4, "min": 5, "and": 6, "or": 7, "xor": 8}
 _DT = {np.dtype(np.float64): 0, np.dtype(np.float32): 1, np.dtype(np.int32): 2}
 
-# Digit widths of the split formats: a signed digit of beta bits has
+# Default digit widths of the split formats: a signed digit of beta bits has
 # |sigma| <= 2**(beta-1), which must be an exactly representable integer in
-# the slice format (BF16: 8 significand bits, so 128 fits; FP8 E4M3: 4 bits,
-# so 16 fits).
+# the slice format. BF16 (8 significand bits) holds every integer of
+# magnitude <= 256, so beta = 9 fits as well (the width the GPU path uses,
+# always passed explicitly); the default 8 keeps |sigma| <= 128. FP8 E4M3
+# (4 significand bits) holds integers up to 16: beta = 5.
 SPLIT_BETA = {"bf16": 8, "fp8": 5}
 
 _lib = None
@@ -230,3 +235,36 @@ def normwise_error(x, ref):
     den = np.linalg.norm(ref.ravel())
     num = np.linalg.norm((x - ref).ravel())
     return float(num / den) if den > 0 else float(num)
+
+
+def maxnorm_error(x, ref):
+    """max |x - ref| / max |ref| in FP64."""
+    x = np.asarray(x, dtype=np.float64, order="C")
+    ref = np.asarray(ref, dtype=np.float64, order="C")
+    den = float(np.abs(ref).max()) if ref.size else 0.0
+    num = float(np.abs(x - ref).max()) if ref.size else 0.0
+    return num / den if den > 0 else num
+
+
+def abs_product(a, b, rows=None):
+    """(|A| (+,*) |B|) in FP64: the scale of a (+,*) result's rounding error,
+    element by element (Eq. inner with both operands replaced by their
+    magnitudes). rows: as for :func:`inner`."""
+    a = np.abs(np.asarray(a, dtype=np.float64, order="C"))
+    b = np.abs(np.asarray(b, dtype=np.float64, order="C"))
+    return inner(a, b, "add", "mul", rows=rows)
+
+
+def componentwise_error(x, ref, scale):
+    """max over elements of |x - ref| / scale, with scale = abs_product(A, B)
+    of the same elements. Where scale is 0 the result is exactly 0, so any
+    difference there gives inf."""
+    x = np.asarray(x, dtype=np.float64, order="C")
+    ref = np.asarray(ref, dtype=np.float64, order="C")
+    scale = np.asarray(scale, dtype=np.float64, order="C")
+    d = np.abs(x - ref)
+    if not d.size:
+        return 0.0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(scale > 0, d / np.where(scale > 0, scale, 1.0), np.where(d > 0, np.inf, 0.0))
+    return float(r.max())

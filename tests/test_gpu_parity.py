@@ -405,10 +405,16 @@ def test_split_full_size_sampled():
     got = host(d[torch.from_numpy(rows).to(DEV)])
     ref = oracle.inner_dot2(a, b, rows=rows)
     e = nerr(got, ref)
-    say("split 8192^3 err vs Dot2 %.3e" % e)
+    scale = oracle.abs_product(a, b, rows=rows)
+    cw = oracle.componentwise_error(got, ref, scale)
+    say("split 8192^3 vs Dot2: normwise %.3e, max-norm %.3e, componentwise %.3e"
+        % (e, oracle.maxnorm_error(got, ref), cw))
     assert e <= 1e-12
     want = oracle.split_inner(a, b, nslices=5, beta=9, rows=rows[:6])
     assert nerr(got[:6], want) <= 1e-14
+    # Element by element the GPU carries the scheme's own truncation error.
+    cw_scheme = oracle.componentwise_error(want, ref[:6], scale[:6])
+    assert oracle.componentwise_error(got[:6], ref[:6], scale[:6]) <= 1.1 * cw_scheme + 1e-16
 
 
 @pytest.mark.parametrize("shape", [(100, 300, 70), (64, 32, 128), (1, 1, 1), (257, 1000, 131), (33, 65, 200)])
@@ -446,11 +452,16 @@ def test_split_int8_full_size_sampled():
     d = moa.inner_split(gpu(a), gpu(b), "int8", 7)
     rows = _sample_rows(np.random.default_rng(9), 8192, 10)
     got = host(d[torch.from_numpy(rows).to(DEV)])
-    e = nerr(got, oracle.inner_dot2(a, b, rows=rows))
-    say("split int8 8192^3 err vs Dot2 %.3e" % e)
+    ref = oracle.inner_dot2(a, b, rows=rows)
+    e = nerr(got, ref)
+    scale = oracle.abs_product(a, b, rows=rows)
+    say("split int8 8192^3 vs Dot2: normwise %.3e, max-norm %.3e, componentwise %.3e"
+        % (e, oracle.maxnorm_error(got, ref), oracle.componentwise_error(got, ref, scale)))
     assert e <= 1e-12
     want = oracle.split_inner(a, b, nslices=7, beta=7, rows=rows[:4])
     assert nerr(got[:4], want) <= 1e-14
+    cw_scheme = oracle.componentwise_error(want, ref[:4], scale[:4])
+    assert oracle.componentwise_error(got[:4], ref[:4], scale[:4]) <= 1.1 * cw_scheme + 1e-16
 
 
 # ---------------------------------------------------------------------------
@@ -779,7 +790,14 @@ def test_plain_fp64_8192_sampled():
     say("plain fp64 8192^3")
     d = host(moa.inner(gpu(a), gpu(b)))
     rows = np.sort(np.random.default_rng(140).choice(8192, 12, replace=False))
-    assert nerr(d[rows], oracle.inner_dot2(a, b, rows=rows)) <= 1e-13
+    ref = oracle.inner_dot2(a, b, rows=rows)
+    assert nerr(d[rows], ref) <= 1e-13
+    # Any summation order of K rounded products stays within gamma_K |A||B|.
+    u = 2.0 ** -53
+    gamma = 8192 * u / (1 - 8192 * u)
+    cw = oracle.componentwise_error(d[rows], ref, oracle.abs_product(a, b, rows=rows))
+    say("plain fp64 8192^3 componentwise %.3e (gamma_K %.3e)" % (cw, gamma))
+    assert cw <= gamma
 
 
 def test_axes_bench_config_sampled():

@@ -500,3 +500,38 @@ def test_inner_axes_operand_swap_transposes_result():
         d = oracle.inner_axes(a, 1, b, 1, op1, op2)            # axes (2, 3, 4)
         e = oracle.inner_axes(b, 1, a, 1, op1, op2)            # axes (4, 2, 3)
         _equal(np.moveaxis(e, 0, -1), d)
+
+
+def test_error_measures_pins():
+    # Max-norm: hand values.
+    assert oracle.maxnorm_error([1.0, -4.0, 2.0], [1.0, -4.0, 2.0]) == 0.0
+    assert oracle.maxnorm_error([1.0, -4.5, 2.0], [1.0, -4.0, 2.0]) == 0.125
+    # |A| . |B| against brute-force sums of magnitudes.
+    a = np.array([[1.0, -2.0, 3.0], [-4.0, 0.5, -1.0]])
+    b = np.array([[-1.0, 2.0], [3.0, -0.25], [0.0, -8.0]])
+    want = np.array([[sum(abs(a[i, l]) * abs(b[l, j]) for l in range(3)) for j in range(2)] for i in range(2)])
+    assert np.array_equal(oracle.abs_product(a, b), want)
+    # Componentwise: hand values, zero scale.
+    assert oracle.componentwise_error([[3.5]], [[3.0]], [[7.0]]) == 0.5 / 7.0
+    assert oracle.componentwise_error([0.0, 1.0], [0.0, 1.0], [0.0, 2.0]) == 0.0
+    assert oracle.componentwise_error([1e-300, 1.0], [0.0, 1.0], [0.0, 2.0]) == np.inf
+
+
+def test_componentwise_error_meets_recursive_summation_bound():
+    # A sequential FP32 fold of FP32 operands satisfies |fl - exact| <= gamma_K (|A||B|)
+    # with gamma_K = K u / (1 - K u), u = 2^-24 (the textbook bound for a
+    # recursively summed dot product); the measured error must sit below it.
+    rng = np.random.default_rng(77)
+    K = 300
+    a = rng.uniform(-1, 1, (20, K)).astype(np.float32)
+    b = rng.uniform(-1, 1, (K, 30)).astype(np.float32)
+    got = oracle.inner(a, b, mode="native")
+    ref = oracle.inner_dot2(a, b)
+    u = 2.0 ** -24
+    gamma = K * u / (1 - K * u)
+    err = oracle.componentwise_error(got, ref, oracle.abs_product(a, b))
+    assert 0 < err <= gamma
+    # With the signed products in place of magnitudes the "scale" can cancel
+    # to near zero and the same error exceeds the bound.
+    bad = oracle.componentwise_error(got, ref, np.abs(oracle.inner(a.astype(np.float64), b.astype(np.float64))))
+    assert bad > err
