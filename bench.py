@@ -97,6 +97,22 @@ def cpu_baseline(a, b, target_s=12.0):
                       (nrows, ops, dt)}
 
 
+def cpu_oracle_small_single_thread():
+    """The oracle on the FP64 512^3 product with one thread (the paper's
+    sequential mode), in a child process so OpenMP starts with one thread."""
+    import subprocess
+    code = ("import json, sys, time; sys.path.insert(0, %r); import moa_inputs as mi, oracle; "
+            "a, b, _, _ = mi.workload_small_mixed(); oracle.inner(a[:8], b); t = time.perf_counter(); "
+            "oracle.inner(a, b); dt = time.perf_counter() - t; "
+            "print(json.dumps({'value': 2.0 * 512 ** 3 / dt / 1e9, 'unit': 'Gop/s', 'ms': dt * 1e3, "
+            "'cores': 1, 'kind': 'oracle', 'sample': 'FP64 512^3, whole product, one thread'}))" % ROOT)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def _time_events(fn, steps, warmup):
     """Average ms of fn() over `steps` runs, HIP events on the current stream."""
     import torch
@@ -454,6 +470,7 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(a_h, b_h)
+        result["cpu_oracle_512_one_thread"] = cpu_oracle_small_single_thread()
     print(json.dumps(result), flush=True)
 
 
