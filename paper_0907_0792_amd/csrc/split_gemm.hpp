@@ -291,7 +291,9 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_i8(
   __shared__ intx4 lds[kNBuf][C::ST_CH * 64];
 
   int64_t tm, tn;
-  grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
+  // 4 tile rows per group as in the BF16 kernel (12.94 ms against 13.03-13.14
+  // ms with 8 rows at 8192^3).
+  grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 4, tm, tn);
   const int tid = threadIdx.x, lane = tid % 64;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int wm = wave / WNW, wn = wave % WNW;
