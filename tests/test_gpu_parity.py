@@ -620,6 +620,7 @@ AXES_CASES = [
     ((17, 130), 0, (17,), 0),              # A stored K x M, vector result
     ((5, 36, 8), 1, (12, 36, 20), 1),      # inner extents multiples of 4: vector panels, strided
     ((9, 40, 4), 1, (7, 40), 1),           # A strided (Qa = 4), B stored N x K (K = 40)
+    ((48, 132), 0, (68, 48), 1),           # A stored K x M, B stored N x K, vector panels, ragged
 ]
 
 
