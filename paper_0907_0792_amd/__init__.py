@@ -142,6 +142,15 @@ def _dev_operands(*ts):
     return dev
 
 
+def _check_out(out, rs, dtype, dev):
+    """A caller-supplied result tensor: right shape, dtype, dense layout and
+    device (the library writes rs elements from its first address)."""
+    if tuple(out.shape) != tuple(rs) or out.dtype != dtype or not out.is_contiguous():
+        raise ValueError("out has the wrong shape, dtype or layout")
+    if not out.is_cuda or out.device != dev:
+        raise ValueError("out must be on the operands' device")
+
+
 def inner_shape(sa, sb):
     out = (ctypes.c_int64 * (2 * MAX_RANK))()
     r = ctypes.c_int32()
@@ -177,8 +186,8 @@ def inner_axes(a: torch.Tensor, b: torch.Tensor, axes=(-1, 0), op1: str = "add",
     rs = tuple(d for i, d in enumerate(a.shape) if i != ax_a) + tuple(d for i, d in enumerate(b.shape) if i != ax_b)
     if out is None:
         out = torch.empty(rs, dtype=a.dtype, device=dev)
-    elif tuple(out.shape) != rs or out.dtype != a.dtype or not out.is_contiguous():
-        raise ValueError("out has the wrong shape, dtype or layout")
+    else:
+        _check_out(out, rs, a.dtype, dev)
     _check(lib().moa_inner_axes(_shape(a.shape), _ptr(a), ax_a, _shape(b.shape), _ptr(b), ax_b, OPS[op1], OPS[op2],
                                 DTYPES[a.dtype], _ptr(out), flags, _stream(dev)))
     return out
@@ -202,8 +211,8 @@ def inner_ex(a: torch.Tensor, b: torch.Tensor, op1: str = "add", op2: str = "mul
     rs = tuple(a.shape[:-1]) + tuple(b.shape[1:])
     if out is None:
         out = torch.empty(rs, dtype=a.dtype, device=dev)
-    elif tuple(out.shape) != rs or out.dtype != a.dtype or not out.is_contiguous():
-        raise ValueError("out has the wrong shape, dtype or layout")
+    else:
+        _check_out(out, rs, a.dtype, dev)
     _check(lib().moa_inner_ex(_shape(a.shape), _ptr(a), _shape(b.shape), _ptr(b), OPS[op1], OPS[op2],
                               DTYPES[a.dtype], _ptr(out), flags, _stream(dev)))
     return out
@@ -224,8 +233,8 @@ def outer(a: torch.Tensor, b: torch.Tensor, op: str = "mul", out: torch.Tensor |
     rs = tuple(a.shape) + tuple(b.shape)  # rho A ++ rho B; the library validates
     if out is None:
         out = torch.empty(rs, dtype=a.dtype, device=dev)
-    elif tuple(out.shape) != rs or out.dtype != a.dtype or not out.is_contiguous():
-        raise ValueError("out has the wrong shape, dtype or layout")
+    else:
+        _check_out(out, rs, a.dtype, dev)
     _check(lib().moa_outer(_shape(a.shape), _ptr(a), _shape(b.shape), _ptr(b), OPS[op], DTYPES[a.dtype], _ptr(out),
                            _stream(dev)))
     return out
@@ -247,28 +256,49 @@ def inner_split(a: torch.Tensor, b: torch.Tensor, fmt: str = "bf16", nslices: in
     rs = tuple(a.shape[:-1]) + tuple(b.shape[1:])
     if out is None:
         out = torch.empty(rs, dtype=torch.float64, device=dev)
+    else:
+        _check_out(out, rs, torch.float64, dev)
     nbytes = split_workspace_bytes(a.shape, b.shape, fmt, nslices)
     if workspace is None:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    else:
+        _check_workspace(workspace, dev)
     _check(lib().moa_inner_split(_shape(a.shape), _ptr(a), _shape(b.shape), _ptr(b), _ptr(out), SPLIT_FORMATS[fmt],
-                                 nslices, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream(dev)))
+                                 nslices, ctypes.c_void_p(workspace.data_ptr()), _nbytes(workspace), _stream(dev)))
     return out
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def _check_workspace(workspace, dev):
+    if not workspace.is_contiguous() or not workspace.is_cuda or workspace.device != dev:
+        raise ValueError("workspace must be a dense tensor on the operands' device")
 
 
 def split_prepare(a: torch.Tensor, b: torch.Tensor, workspace: torch.Tensor, fmt: str = "bf16", nslices: int = 5):
     """Scan and slice A and B into `workspace` (first half of inner_split)."""
-    dev = _dev_operands(a, b, workspace)
+    if a.dtype != torch.float64 or b.dtype != torch.float64:
+        raise TypeError("split_prepare takes float64 operands")
+    dev = _dev_operands(a, b)
+    _check_workspace(workspace, dev)
+    a = a.contiguous()
+    b = b.contiguous()
     _check(lib().moa_inner_split_prepare(_shape(a.shape), _ptr(a), _shape(b.shape), _ptr(b), SPLIT_FORMATS[fmt],
-                                         nslices, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                         nslices, ctypes.c_void_p(workspace.data_ptr()), _nbytes(workspace),
                                          _stream(dev)))
 
 
 def split_multiply(sa, sb, out: torch.Tensor, workspace: torch.Tensor, fmt: str = "bf16", nslices: int = 5,
                    stream=None):
     """Slice-pair products from `workspace` into `out` (second half of inner_split)."""
+    dev = _dev_operands(out)
+    _check_out(out, tuple(sa[:-1]) + tuple(sb[1:]), torch.float64, dev)
+    _check_workspace(workspace, dev)
     st = stream if stream is not None else _stream(out.device)
     _check(lib().moa_inner_split_multiply(_shape(sa), _shape(sb), _ptr(out), SPLIT_FORMATS[fmt], nslices,
-                                          ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), st))
+                                          ctypes.c_void_p(workspace.data_ptr()), _nbytes(workspace), st))
 
 
 def inner_grad(a, b, g, need_a=True, need_b=True):
@@ -319,6 +349,8 @@ class Batch:
         if not (len(Bs) == n == len(Ds)):
             raise ValueError("A, B, D lists differ in length")
         dt = As[0].dtype if n else torch.float32
+        if n:
+            _dev_operands(*As, *Bs, *Ds)
         self._shapes = []
         sa = (_Shape * max(1, n))()
         sb = (_Shape * max(1, n))()

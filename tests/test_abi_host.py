@@ -229,3 +229,16 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_binding_rejects_host_tensors_before_any_launch():
+    # Host (CPU) tensors never reach the library: every entry checks devices first.
+    import torch
+    a = torch.zeros(4, 4, dtype=torch.float64)
+    b = torch.zeros(4, 4, dtype=torch.float64)
+    for call in (lambda: moa.inner(a, b), lambda: moa.outer(a, b), lambda: moa.inner_axes(a, b, (0, 1)),
+                 lambda: moa.inner_split(a, b), lambda: moa.split_prepare(a, b, torch.zeros(64, dtype=torch.uint8)),
+                 lambda: moa.split_multiply((4, 4), (4, 4), a, torch.zeros(64, dtype=torch.uint8)),
+                 lambda: moa.inner_grad(a, b, a), lambda: moa.Batch([a], [b], [a.clone()])):
+        with pytest.raises(ValueError):
+            call()

@@ -598,6 +598,31 @@ def test_batch_autotune_then_build():
     bt.close()
 
 
+def test_binding_checks_out_workspace_and_layout():
+    # A result or workspace tensor on the host, or of the wrong shape, is
+    # rejected before any launch; non-contiguous operands are made dense.
+    rng = np.random.default_rng(116)
+    a = mi.uniform_f64(rng, (40, 24))
+    b = mi.uniform_f64(rng, (24, 30))
+    ga, gb = gpu(a), gpu(b)
+    with pytest.raises(ValueError):
+        moa.inner(ga, gb, out=torch.empty(40, 30, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        moa.outer(ga, gb, out=torch.empty(40, 24, 30, 24, dtype=torch.float64, device=DEV))
+    with pytest.raises(ValueError):
+        moa.inner_split(ga, gb, workspace=torch.empty(1 << 20, dtype=torch.uint8))
+    # Expanded (stride-0) and transposed views as split operands.
+    at = gpu(np.ascontiguousarray(a.T)).t()
+    bx = gpu(b[:1]).expand(24, 30)
+    ref = moa.inner_split(gpu(a), gpu(np.repeat(b[:1], 24, axis=0)))
+    ws = torch.empty(moa.split_workspace_bytes((40, 24), (24, 30)), dtype=torch.uint8, device=DEV)
+    out = torch.empty(40, 30, dtype=torch.float64, device=DEV)
+    say("split two-stage on strided views")
+    moa.split_prepare(at, bx, ws)
+    moa.split_multiply((40, 24), (24, 30), out, ws)
+    eq(host(out), host(ref))
+
+
 def test_errors_on_device_tensors():
     a = gpu(np.ones((3, 4)))
     b = gpu(np.ones((5, 2)))
