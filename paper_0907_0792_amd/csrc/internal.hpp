@@ -44,6 +44,12 @@ hipError_t launch_outer(moa_dtype dt, moa_op op, const void *A, const void *B, v
 hipError_t launch_gemm(moa_dtype dt, bool trans_a, bool trans_b, const void *A, const void *B, void *D, int64_t M,
                        int64_t K, int64_t N, int tile, hipStream_t s);
 
+// Both products of the (+,*) backward, dA (M x K) = G (M x N) . B^T and
+// dB (K x N) = A^T . G, with A stored M x K, B stored K x N, G stored M x N;
+// one launch when both products take the same tile size. M, K, N > 0.
+hipError_t launch_gemm_grad(moa_dtype dt, const void *G, const void *A, const void *B, void *dA, void *dB, int64_t M,
+                            int64_t K, int64_t N, hipStream_t s);
+
 // (+,*) on the matrix cores over the strided views above (general axes).
 hipError_t launch_gemm_strided(moa_dtype dt, const void *A, const void *B, void *D, int64_t M, int64_t K, int64_t N,
                                int64_t Qa, int64_t Qb, hipStream_t s);

@@ -34,16 +34,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm(const T *__restrict__ A, const 
                                                                              tn * 32 * WBN, Qa, Qb);
 }
 
+// The largest tile that still gives the CUs enough workgroups: 128 x 128
+// (1) from 512 tiles up, 64 x 64 (2) from 256 (one per CU), else 32 x 32 (3).
+static int auto_tile(int64_t M, int64_t N) {
+  const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
+  const int64_t mid = ((M + 63) / 64) * ((N + 63) / 64);
+  return big >= 512 ? 1 : mid >= 256 ? 2 : 3;
+}
+
 template <typename T, bool TA, bool TB, bool GEN, bool VEC>
 static hipError_t launch_t(const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile, int64_t Qa,
                            int64_t Qb, hipStream_t s) {
-  if (tile == 0) {
-    // The largest tile that still gives the CUs enough workgroups: 128 x 128
-    // from 512 tiles up, 64 x 64 from 256 (one per CU), else 32 x 32.
-    const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
-    const int64_t mid = ((M + 63) / 64) * ((N + 63) / 64);
-    tile = big >= 512 ? 1 : mid >= 256 ? 2 : 3;
-  }
+  if (tile == 0) tile = auto_tile(M, N);
   if (tile == 3) {
     const int64_t tmn = (M + 31) / 32, tnn = (N + 31) / 32;
     if (tmn * tnn > 0x7fffffff) return hipErrorInvalidConfiguration;
@@ -124,6 +126,78 @@ hipError_t launch_gemm_strided(moa_dtype dt, const void *A, const void *B, void 
     return launch_tt<float, true>(ta, tb, vec_ok(a, b, a_run, b_run), a, b, (float *)D, M, K, N, 0, Qa, Qb, s);
   }
   return hipErrorInvalidValue;
+}
+
+// The two products of the backward pass in one launch: workgroups [0, n0)
+// take tiles of dA = G . B^T (B read as stored, K x N = (N x K)^T), the rest
+// tiles of dB = A^T . G (A read as stored). One launch instead of two: no gap
+// between them, and the second product's tiles fill the CUs the first one's
+// tail leaves idle.
+struct GemmJob {
+  const void *A;
+  const void *B;
+  void *D;
+  int64_t M, K, N, tiles_m, tiles_n;
+};
+
+template <typename T, int WBM, int WBN, bool VEC>
+__global__ __launch_bounds__(256, 2) void k_gemm_grad_pair(GemmJob j0, GemmJob j1) {
+  const int64_t n0 = j0.tiles_m * j0.tiles_n;
+  int64_t tm, tn;
+  if ((int64_t)blockIdx.x < n0) {
+    grouped_tile(xcd_swizzle(blockIdx.x, n0), j0.tiles_m, j0.tiles_n, 8, tm, tn);
+    gemm_tile<T, false, true, WBM, WBN, sizeof(T) == 4 ? 32 : 16, false, false, VEC>(
+        (const T *)j0.A, (const T *)j0.B, (T *)j0.D, j0.M, j0.K, j0.N, tm * 32 * WBM, tn * 32 * WBN);
+  } else {
+    const int64_t b = blockIdx.x - n0, n1 = j1.tiles_m * j1.tiles_n;
+    grouped_tile(xcd_swizzle(b, n1), j1.tiles_m, j1.tiles_n, 8, tm, tn);
+    gemm_tile<T, true, false, WBM, WBN, sizeof(T) == 4 ? 32 : 16, false, false, VEC>(
+        (const T *)j1.A, (const T *)j1.B, (T *)j1.D, j1.M, j1.K, j1.N, tm * 32 * WBM, tn * 32 * WBN);
+  }
+}
+
+template <typename T, int WB, bool VEC>
+static hipError_t launch_pair_t(GemmJob j0, GemmJob j1, hipStream_t s) {
+  constexpr int side = 32 * WB;
+  j0.tiles_m = (j0.M + side - 1) / side;
+  j0.tiles_n = (j0.N + side - 1) / side;
+  j1.tiles_m = (j1.M + side - 1) / side;
+  j1.tiles_n = (j1.N + side - 1) / side;
+  const int64_t blocks = j0.tiles_m * j0.tiles_n + j1.tiles_m * j1.tiles_n;
+  if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_gemm_grad_pair<T, WB, WB, VEC>), dim3((unsigned)blocks), dim3(256), 0, s, j0, j1);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_pair(const T *G, const T *A, const T *B, T *dA, T *dB, int64_t M, int64_t K, int64_t N,
+                              hipStream_t s) {
+  // dA (M x K) = G (M x N) . B^T ; dB (K x N) = A^T . G.
+  const GemmJob j0{G, B, dA, M, N, K, 0, 0}, j1{A, G, dB, K, M, N, 0, 0};
+  const int tile = auto_tile(M, K);
+  const bool vec = vec_ok(G, B, N, N) && vec_ok(A, G, K, N);
+  if (tile != auto_tile(K, N))  // different tile sizes: two launches
+    return hipErrorNotSupported;
+  if (tile == 1) return vec ? launch_pair_t<T, 4, true>(j0, j1, s) : launch_pair_t<T, 4, false>(j0, j1, s);
+  if (tile == 2) return vec ? launch_pair_t<T, 2, true>(j0, j1, s) : launch_pair_t<T, 2, false>(j0, j1, s);
+  return vec ? launch_pair_t<T, 1, true>(j0, j1, s) : launch_pair_t<T, 1, false>(j0, j1, s);
+}
+
+hipError_t launch_gemm_grad(moa_dtype dt, const void *G, const void *A, const void *B, void *dA, void *dB, int64_t M,
+                            int64_t K, int64_t N, hipStream_t s) {
+  hipError_t e = hipErrorNotSupported;
+  if (M > 0 && K > 0 && N > 0) {
+    if (dt == MOA_F64)
+      e = launch_pair<double>((const double *)G, (const double *)A, (const double *)B, (double *)dA, (double *)dB,
+                              M, K, N, s);
+    else if (dt == MOA_F32)
+      e = launch_pair<float>((const float *)G, (const float *)A, (const float *)B, (float *)dA, (float *)dB, M, K,
+                             N, s);
+  }
+  if (e != hipErrorNotSupported) return e;
+  // Tile sizes differ between the two products: one launch each.
+  if ((e = launch_gemm(dt, false, true, G, B, dA, M, N, K, 0, s)) != hipSuccess) return e;
+  return launch_gemm(dt, true, false, A, G, dB, K, M, N, 0, s);
 }
 
 }  // namespace moa

@@ -409,6 +409,9 @@ moa_status moa_inner_grad(moa_shape sa, const void *A, moa_shape sb, const void 
              (dA && overlaps(dB, bB, dA, bA))))
     return fail(MOA_ERR_ALIAS, "dB overlaps an input or dA");
   hipStream_t s = (hipStream_t)stream;
+  // Both gradients of a non-degenerate product: one paired launch.
+  if (dA && dB && f.M > 0 && f.K > 0 && f.N > 0)
+    return hip_status(moa::launch_gemm_grad(dt, G, A, B, dA, dB, f.M, f.K, f.N, s), "grad dA, dB");
   // dA (M x K) = G (M x N) . B^T, B stored K x N = (N x K)^T.
   if (dA && f.nA > 0) {
     hipError_t e = (f.N == 0) ? moa::launch_fill_identity(dt, MOA_ADD, dA, f.nA, s)

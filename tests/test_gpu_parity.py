@@ -518,6 +518,33 @@ def test_grad_full_size_vs_oracle():
     assert nerr(host(d.detach()), oracle.inner(a, b)) <= 1e-5
 
 
+@pytest.mark.parametrize("dt,tol", [(np.float32, 1e-5), (np.float64, 1e-13)])
+def test_grad_shapes_paired_and_separate(dt, tol):
+    # Both gradients in one launch when dA and dB take the same tile size
+    # (ragged edges included), two launches when they do not (last shape:
+    # dA 8192 x 2048 in 128 x 128 tiles, dB 2048 x 64 in 32 x 32), and only
+    # the requested one when the other is not needed.
+    rng = np.random.default_rng(117)
+    for M, K, N in [(37, 53, 29), (300, 70, 130), (4100, 36, 260), (8192, 2048, 64)]:
+        a = mi.uniform_f64(rng, (M, K)).astype(dt)
+        b = mi.uniform_f64(rng, (K, N)).astype(dt)
+        g = mi.uniform_f64(rng, (M, N)).astype(dt)
+        say("grad", np.dtype(dt).name, M, K, N)
+        da, db = moa.inner_grad(gpu(a), gpu(b), gpu(g))
+        rows = None if M <= 4100 else np.sort(rng.choice(M, 16, replace=False))
+        ref_da = oracle.inner_dot2(g, np.ascontiguousarray(b.T), rows=rows)
+        got_da = host(da) if rows is None else host(da)[rows]
+        assert nerr(got_da, ref_da) <= tol
+        assert nerr(host(db), oracle.inner_dot2(np.ascontiguousarray(a.T), g)) <= tol
+    a = mi.uniform_f64(rng, (70, 40)).astype(dt)
+    b = mi.uniform_f64(rng, (40, 90)).astype(dt)
+    g = mi.uniform_f64(rng, (70, 90)).astype(dt)
+    da, db = moa.inner_grad(gpu(a), gpu(b), gpu(g), need_a=True, need_b=False)
+    assert db is None and nerr(host(da), oracle.inner_dot2(g, np.ascontiguousarray(b.T))) <= tol
+    da, db = moa.inner_grad(gpu(a), gpu(b), gpu(g), need_a=False, need_b=True)
+    assert da is None and nerr(host(db), oracle.inner_dot2(np.ascontiguousarray(a.T), g)) <= tol
+
+
 # ---------------------------------------------------------------------------
 # Batching.
 
