@@ -292,6 +292,21 @@ def test_mfma_vector_panels_ragged_and_misaligned(dt, tol):
         assert nerr(host(moa.inner(av, bv)), ref) <= tol
 
 
+def test_mfma_f32_large_tiles_transposed_operands():
+    # FP32 products in 128 x 128 tiles (32-bit index kernel) with A stored
+    # K x M and B stored K x N or N x K, ragged edges (M = N = 3000).
+    rng = np.random.default_rng(118)
+    a = mi.uniform_f64(rng, (64, 3000)).astype(np.float32)
+    for sb, ax_b in (((64, 3000), 0), ((3000, 64), 1)):
+        b = mi.uniform_f64(rng, sb).astype(np.float32)
+        say("mfma f32 large tiles, axes", (0, ax_b))
+        got = host(moa.inner_axes(gpu(a), gpu(b), (0, ax_b)))
+        am, bm = _moved(a, 0, b, ax_b)
+        rows = np.sort(rng.choice(3000, 20, replace=False))
+        ref = oracle.inner_dot2(np.ascontiguousarray(am), np.ascontiguousarray(bm), rows=rows)
+        assert nerr(got[rows], ref) <= 1e-5
+
+
 def test_mfma_f64_exact_integers():
     # Integer entries with |x| <= 8 and K <= 8192: every partial sum is exact,
     # so any summation order gives the exact product.
