@@ -58,6 +58,25 @@ __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const 
 
   for (int64_t k0 = 0; k0 < K; k0 += kChunk) {
     const int kc = (K - k0) < kChunk ? (int)(K - k0) : kChunk;
+    // A values of a full chunk are loaded first, so their latency overlaps
+    // the staging of B and its barriers.
+    T x[NSPAN][R][VW];
+    if (kc == kChunk) {
+#pragma unroll
+      for (int h = 0; h < NSPAN; ++h)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const T *src = a[r] + k0 + h * SPAN + VW * lane;
+          if (vec) {
+            const vec_t v = *(const vec_t *)src;
+#pragma unroll
+            for (int u = 0; u < VW; ++u) x[h][r][u] = v[u];
+          } else {
+#pragma unroll
+            for (int u = 0; u < VW; ++u) x[h][r][u] = src[u];
+          }
+        }
+    }
     // Stage rows k0 .. k0 + kc - 1 of B (one contiguous block of kc N):
     // thread t takes column t % NP of rows t / NP + j 256 / NP (NP = NC
     // rounded up to a power of two, so no division by N). When N = NP and the
@@ -85,18 +104,6 @@ __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const 
     for (int h = 0; h < NSPAN; ++h) {
       const int l0 = h * SPAN + VW * lane;  // this lane's first l in the chunk
       if (kc == kChunk) {
-        T x[R][VW];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          if (vec) {
-            const vec_t v = *(const vec_t *)(a[r] + k0 + l0);
-#pragma unroll
-            for (int u = 0; u < VW; ++u) x[r][u] = v[u];
-          } else {
-#pragma unroll
-            for (int u = 0; u < VW; ++u) x[r][u] = a[r][k0 + l0 + u];
-          }
-        }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           if (c < N) {
@@ -107,8 +114,8 @@ __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const 
             for (int r = 0; r < R; ++r)
 #pragma unroll
               for (int u = 0; u < VW; u += 2)  // pairs of terms (three-operand fold for int32)
-                acc[r][c] = fold_pair<OP1>(acc[r][c], apply_op<OP2>(x[r][u], b[u]),
-                                           apply_op<OP2>(x[r][u + 1], b[u + 1]));
+                acc[r][c] = fold_pair<OP1>(acc[r][c], apply_op<OP2>(x[h][r][u], b[u]),
+                                           apply_op<OP2>(x[h][r][u + 1], b[u + 1]));
           }
         }
       } else {
@@ -116,15 +123,15 @@ __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const 
         for (int u = 0; u < VW; ++u) {
           const int l = l0 + u;
           if (l < kc) {
-            T x[R];
+            T xt[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) x[r] = a[r][k0 + l];
+            for (int r = 0; r < R; ++r) xt[r] = a[r][k0 + l];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
               if (c < N) {
                 const T bv = Bs[(h * SPAN + u * kWave + lane) * SB + c];
 #pragma unroll
-                for (int r = 0; r < R; ++r) acc[r][c] = apply_op<OP1>(acc[r][c], apply_op<OP2>(x[r], bv));
+                for (int r = 0; r < R; ++r) acc[r][c] = apply_op<OP1>(acc[r][c], apply_op<OP2>(xt[r], bv));
               }
           }
         }
