@@ -22,7 +22,8 @@ same fields, their own roofline): plain64 (FP64 (+,*) 8192^3), rank5 (FP64
 (FP32 (-) <512 512> o <64 64>), batch (10,000 uneven FP32 products, one graph
 launch), grad (FP32 forward + backward <32 128 512>.<512 64 64>), small
 (FP64 512^3 plus the <32 32> o <16 16> outer product), skinny (the paper's
-own FP64 4 x 128 . 128 x 2^22 product, HBM-bound), axes (FP64 <16 2048 512>
+own FP64 4 x 128 . 128 x 2^22 product, HBM-bound), skinny_sweep (the same for m = 1..4
+and n = 2^16..2^22, the analogue of the paper's timing curves), axes (FP64 <16 2048 512>
 . <16 2048 512> contracted over axes (1, 1), read in place), fewcols (int32
 (max,+) 65536 x 4096 . 4096 x 8, wavefront-reduced fold).
 """
@@ -227,6 +228,30 @@ def other_workload(args):
                     roofline={"bound": "hbm", "kernel": "k_skinny<double, add, mul, MR=%d, R=4>" % m, "achieved": round(gbs, 2),
                               "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                               "traffic": None})
+    if w == "skinny_sweep":
+        # The paper's experiment shape (Section II.B): m x 128 . 128 x n for
+        # m = 1..4 and growing n, as GB/s against the HBM roofline.
+        rows = []
+        for lg in (16, 18, 20, 22):
+            n = 1 << lg
+            a_h, b_h = mi.workload_skinny(m=4, n=n)
+            a4, b = put(a_h), put(b_h)
+            for m in (1, 2, 3, 4):
+                a = a4[:m].contiguous()
+                out = torch.empty((m, n), dtype=torch.float64, device=dev)
+                ms, _ = _time_events(lambda: moa.inner(a, b, out=out), args.steps, args.warmup)
+                nbytes = 8.0 * (128 * n + m * n + m * 128)
+                rows.append({"m": m, "n": n, "ms": round(ms, 4), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                             "Gflop/s": round(2.0 * m * 128 * n / (ms * 1e-3) / 1e9, 1)})
+            del a4, b, a, out
+        best = max(r["GB/s"] for r in rows)
+        return dict(base, metric="few-row inner product GB/s (sweep)", value=best, unit="GB/s",
+                    ms_per_step=rows[-1]["ms"], dtype="f64",
+                    config={"workload": "FP64 (+,*) m x 128 . 128 x n, m = 1..4, n = 2^16..2^22, U[-1,1]"},
+                    sweep=rows,
+                    roofline={"bound": "hbm", "kernel": "k_skinny<double, add, mul>", "achieved": best,
+                              "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(best / PEAK_HBM_GBS, 4),
+                              "traffic": None})
     if w == "tropical":
         a_h, b_h = mi.workload_tropical()
         a, b = put(a_h), put(b_h)
@@ -310,7 +335,7 @@ def main():
     ap.add_argument("--plain-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="split",
-                    choices=["split", "plain64", "rank5", "tropical", "outer", "batch", "grad", "small", "skinny",
+                    choices=["split", "plain64", "rank5", "tropical", "outer", "batch", "grad", "small", "skinny", "skinny_sweep",
                              "axes", "fewcols"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration)")

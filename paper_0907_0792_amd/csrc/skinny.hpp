@@ -27,10 +27,16 @@ namespace moa {
 // and row, which keeps enough bytes in flight per CU with fewer waves.
 // MR: rows held per thread (1, 2, 4 or 8; rows M..MR-1 repeat row M - 1 and
 // are never stored).
+// blockIdx.y selects a group of MR rows (a grid with gridDim.y > 1 splits
+// the rows over workgroups: each reads B again, from cache when B is small).
 template <typename T, int OP1, int OP2, int MR, int R>
 __global__ __launch_bounds__(256) void k_skinny(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
                                                 int M, int64_t K, int64_t N, bool vec_ok) {
   constexpr int VEC = 16 / sizeof(T);
+  const int row0 = (int)blockIdx.y * MR;
+  A += (int64_t)row0 * K;
+  D += (int64_t)row0 * N;
+  M = M - row0 < MR ? M - row0 : MR;
   constexpr int64_t SPAN = 256 * VEC;  // columns between a thread's runs
   const int64_t blk0 = (int64_t)blockIdx.x * SPAN * R;
   const int64_t j0 = blk0 + threadIdx.x * VEC;
@@ -101,6 +107,17 @@ static hipError_t launch_mr(const T *A, const T *B, T *D, int64_t M, int64_t K, 
   // 16-byte loads of B rows need N % VEC == 0 and a 16-byte aligned B.
   const bool vec_ok = (N % VEC) == 0 && ((uintptr_t)B % 16) == 0;
   const int m = (int)M;
+  // Few column blocks, several rows and a B small enough to stay in the
+  // last-level cache (256 MB on MI355X; B is then read from HBM about once):
+  // one row per workgroup row instead, so the GPU holds M times as many
+  // waves and the dependency chain of one thread's fold no longer decides
+  // the time (3-4 rows of 128 . 128 x 2^16 FP64: 53 us with four rows per
+  // thread). Larger B keeps all rows in one pass, reading B once.
+  if (M > 2 && blocks < 1024 && K * N * (int64_t)sizeof(T) <= ((int64_t)64 << 20)) {
+    hipLaunchKernelGGL((k_skinny<T, OP1, OP2, 1, R>), dim3((unsigned)blocks, (unsigned)M), b, 0, s, A, B, D, m, K, N,
+                       vec_ok);
+    return hipGetLastError();
+  }
   if (M == 1)
     hipLaunchKernelGGL((k_skinny<T, OP1, OP2, 1, R>), g, b, 0, s, A, B, D, m, K, N, vec_ok);
   else if (M == 2)
