@@ -35,7 +35,7 @@
  * FP64 / FP32 runs on the matrix cores in another summation order (normwise
  * relative error of order K * unit roundoff), except for results with at most
  * 8 rows (product of rhoA[:-1]) and at least 4096 columns, which stream B
- * once and fold in ascending p like every other pair. Folds whose value does
+ * from memory and fold in ascending p like every other pair. Folds whose value does
  * not depend on association (every int32 op1, FP max and min) may be combined
  * in any order: with at most 16 columns and K >= 256 the terms are split over
  * the lanes of a wave and combined by a cross-lane reduction (same value;
