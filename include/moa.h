@@ -30,16 +30,19 @@
  * (+: 0, *: 1, max: -inf / INT32_MIN, min: +inf / INT32_MAX, and: ~0, or/xor: 0).
  *
  * Arithmetic. int32 +, -, * wrap (two's complement); max/min are signed.
+ * FP max/min are the IEEE 754-2019 maximum/minimum: a NaN operand gives NaN
+ * and -0 is ordered below +0, which makes them associative and commutative.
  * FP (op1, op2) pairs other than (+,*) fold in ascending p, one IEEE
- * operation per step, so they match a sequential fold bit for bit. (+,*) on
+ * operation per step, so they match a sequential fold bit for bit, signed
+ * zeros included (NaN payloads are not specified). (+,*) on
  * FP64 / FP32 runs on the matrix cores in another summation order (normwise
  * relative error of order K * unit roundoff), except for results with at most
  * 8 rows (product of rhoA[:-1]) and at least 4096 columns, which stream B
  * from memory and fold in ascending p like every other pair. Folds whose value does
  * not depend on association (every int32 op1, FP max and min) may be combined
  * in any order: with at most 16 columns and K >= 256 the terms are split over
- * the lanes of a wave and combined by a cross-lane reduction (same value;
- * for FP max/min a zero result's sign can differ where +0 and -0 tie).
+ * the lanes of a wave and combined by a cross-lane reduction (the same
+ * value, bit for bit).
  *
  * Errors. Every call validates on the host before any launch and returns a
  * moa_status; nothing is launched on an error. Kernel execution is
@@ -199,10 +202,13 @@ moa_status moa_inner_grad(moa_shape sa, const void *A, moa_shape sb, const void 
 /* ---------------------------------------------------------------------------
  * Batches of uneven (+,*) inner products in one persistent launch.
  *
- * moa_batch_build validates every problem on the host, uploads a device
- * descriptor table (problem shapes, pointers, tile choice per problem from the
- * tile table), orders the work by estimated cost, and captures the persistent
- * launch in a HIP graph on `stream`. The caller's A[i], B[i], D[i] (device
+ * moa_batch_build validates every problem on the host, orders the work by
+ * estimated cost, uploads a device descriptor table (problem shapes,
+ * pointers, tile choice per problem from the tile table) and work list on
+ * `stream`, waits for that upload, and captures the persistent launch in a
+ * HIP graph (on a private stream: capture is not allowed on the default
+ * stream). Each D[i] must hold the whole result of problem i (its shape is
+ * that of moa_inner_shape(sa[i], sb[i])). The caller's A[i], B[i], D[i] (device
  * pointers, dtype dt = MOA_F32 or MOA_F64) must stay valid while the batch
  * exists; moa_batch_run replays the graph (one kernel launch). A batch owns
  * only its descriptor table, work list and graph; moa_batch_free releases
@@ -220,8 +226,12 @@ moa_status moa_batch_info(const moa_batch *b, int64_t *work_items, int32_t *laun
 /* Tile table used by moa_batch_build: for each (M, N, K) size bucket the
  * tile variant to use. moa_batch_autotune times every tile variant on
  * synthetic problems of each bucket on `stream` and installs the fastest;
- * moa_tile_table_get/set read or replace the table as text
- * ("bucket_m bucket_n bucket_k variant" lines). */
+ * moa_tile_table_get/set read or replace the table as text: eight lines
+ * "bucket_m bucket_n bucket_k variant", one per bucket, with bucket_m one of
+ * "M<=32" / "M>32", bucket_n "N<=32" / "N>32", bucket_k "K<=128" / "K>128"
+ * and variant 0 (32 x 32 tiles) or 1 (64 x 64). moa_tile_table_set rejects
+ * (MOA_ERR_ARG, table unchanged) any other token, a bucket given twice or a
+ * missing bucket. */
 moa_status moa_batch_autotune(moa_dtype dt, int32_t reps, void *stream);
 moa_status moa_tile_table_get(char *buf, size_t len);
 moa_status moa_tile_table_set(const char *text);

@@ -24,6 +24,24 @@ def _wrap32(v: int) -> int:
     return v - (1 << 32) if v >= (1 << 31) else v
 
 
+def _fkey(x):
+    # Order of the IEEE 754-2019 maximum / minimum on non-NaN values: by
+    # value, and -0 before +0.
+    return (float(x), math.copysign(1.0, float(x)))
+
+
+def _fmax(a, b):
+    if math.isnan(a) or math.isnan(b):
+        return a + b  # a NaN
+    return a if _fkey(a) >= _fkey(b) else b
+
+
+def _fmin(a, b):
+    if math.isnan(a) or math.isnan(b):
+        return a + b
+    return a if _fkey(a) <= _fkey(b) else b
+
+
 def _apply(op, a, b, kind):
     if kind == "i":
         if op == "add":
@@ -55,9 +73,9 @@ def _apply(op, a, b, kind):
             if op == "div":
                 return np.float32(a / b)
             if op == "max":
-                return b if a < b else a
+                return _fmax(a, b)
             if op == "min":
-                return b if b < a else a
+                return _fmin(a, b)
         raise ValueError(op)
     if op == "add":
         r = a + b
@@ -68,9 +86,9 @@ def _apply(op, a, b, kind):
     elif op == "div":
         r = a / b if b != 0 else (math.copysign(math.inf, a) * math.copysign(1.0, b) if a != 0 else math.nan)
     elif op == "max":
-        r = b if a < b else a
+        r = _fmax(a, b)
     elif op == "min":
-        r = b if b < a else a
+        r = _fmin(a, b)
     else:
         raise ValueError(op)
     return r

@@ -24,6 +24,8 @@
  *     element is the outer product.
  *   - an empty contraction (K = 0) yields the identity of op1.
  *   - int32 +, -, * wrap in two's complement; max/min are signed.
+ *   - FP max/min are the IEEE 754-2019 maximum/minimum (NaN if either
+ *     operand is NaN; -0 below +0).
  *
  * Also here (published methods, not in the paper):
  *   - a compensated (+,*) FP64 dot product, Dot2 of Ogita, Rump & Oishi,
@@ -94,8 +96,16 @@ static double op_f64(int op, double a, double b) {
     case O_SUB: return a - b;
     case O_MUL: return a * b;
     case O_DIV: return a / b;
-    case O_MAX: return (a < b) ? b : a;
-    case O_MIN: return (b < a) ? b : a;
+    /* IEEE 754-2019 maximum / minimum: a NaN operand gives NaN, and -0 is
+     * ordered below +0, so both are associative and commutative. */
+    case O_MAX:
+      if (isnan(a) || isnan(b)) return NAN;
+      if (a == b) return signbit(a) ? b : a;
+      return (a < b) ? b : a;
+    case O_MIN:
+      if (isnan(a) || isnan(b)) return NAN;
+      if (a == b) return signbit(a) ? a : b;
+      return (b < a) ? b : a;
   }
   return NAN;
 }

@@ -151,11 +151,32 @@ def _check_out(out, rs, dtype, dev):
         raise ValueError("out must be on the operands' device")
 
 
-def inner_shape(sa, sb):
+_RESULT_SHAPES = {}
+
+
+def _cached_shape(key, compute):
+    """Result shapes come from the library's shape algebra (moa_*_shape) and
+    are cached per operand-shape key, so the binding keeps no second copy of
+    it and small products do not pay a shape call each."""
+    rs = _RESULT_SHAPES.get(key)
+    if rs is None:
+        rs = compute()
+        if len(_RESULT_SHAPES) < 4096:
+            _RESULT_SHAPES[key] = rs
+    return rs
+
+
+def _shape_call(fn, *args):
     out = (ctypes.c_int64 * (2 * MAX_RANK))()
     r = ctypes.c_int32()
-    _check(lib().moa_inner_shape(_shape(sa), _shape(sb), out, ctypes.byref(r)))
+    _check(fn(*args, out, ctypes.byref(r)))
     return tuple(out[i] for i in range(r.value))
+
+
+def inner_shape(sa, sb):
+    """Result shape of Eq. inner (moa_inner_shape): rho A[:-1] ++ rho B[1:]."""
+    sa, sb = tuple(sa), tuple(sb)
+    return _cached_shape(("inner", sa, sb), lambda: _shape_call(lib().moa_inner_shape, _shape(sa), _shape(sb)))
 
 
 def _axis(ax, rank):
@@ -164,11 +185,11 @@ def _axis(ax, rank):
 
 
 def inner_axes_shape(sa, ax_a, sb, ax_b):
-    out = (ctypes.c_int64 * (2 * MAX_RANK))()
-    r = ctypes.c_int32()
-    _check(lib().moa_inner_axes_shape(_shape(sa), _axis(ax_a, len(sa)), _shape(sb), _axis(ax_b, len(sb)), out,
-                                      ctypes.byref(r)))
-    return tuple(out[i] for i in range(r.value))
+    """Result shape of a contraction over axes (ax_a, ax_b) (moa_inner_axes_shape)."""
+    sa, sb = tuple(sa), tuple(sb)
+    ax_a, ax_b = _axis(ax_a, len(sa)), _axis(ax_b, len(sb))
+    return _cached_shape(("axes", sa, ax_a, sb, ax_b),
+                         lambda: _shape_call(lib().moa_inner_axes_shape, _shape(sa), ax_a, _shape(sb), ax_b))
 
 
 def inner_axes(a: torch.Tensor, b: torch.Tensor, axes=(-1, 0), op1: str = "add", op2: str = "mul", flags: int = 0,
@@ -182,8 +203,7 @@ def inner_axes(a: torch.Tensor, b: torch.Tensor, axes=(-1, 0), op1: str = "add",
     a = a.contiguous()
     b = b.contiguous()
     ax_a, ax_b = _axis(axes[0], a.dim()), _axis(axes[1], b.dim())
-    # A's free axes, then B's; the library validates the axes and extents.
-    rs = tuple(d for i, d in enumerate(a.shape) if i != ax_a) + tuple(d for i, d in enumerate(b.shape) if i != ax_b)
+    rs = inner_axes_shape(a.shape, ax_a, b.shape, ax_b)  # A's free axes, then B's
     if out is None:
         out = torch.empty(rs, dtype=a.dtype, device=dev)
     else:
@@ -194,10 +214,9 @@ def inner_axes(a: torch.Tensor, b: torch.Tensor, axes=(-1, 0), op1: str = "add",
 
 
 def outer_shape(sa, sb):
-    out = (ctypes.c_int64 * (2 * MAX_RANK))()
-    r = ctypes.c_int32()
-    _check(lib().moa_outer_shape(_shape(sa), _shape(sb), out, ctypes.byref(r)))
-    return tuple(out[i] for i in range(r.value))
+    """Result shape of Eq. outer (moa_outer_shape): rho A ++ rho B."""
+    sa, sb = tuple(sa), tuple(sb)
+    return _cached_shape(("outer", sa, sb), lambda: _shape_call(lib().moa_outer_shape, _shape(sa), _shape(sb)))
 
 
 def inner_ex(a: torch.Tensor, b: torch.Tensor, op1: str = "add", op2: str = "mul", flags: int = 0,
@@ -207,8 +226,7 @@ def inner_ex(a: torch.Tensor, b: torch.Tensor, op1: str = "add", op2: str = "mul
     dev = _dev_operands(a, b)
     a = a.contiguous()
     b = b.contiguous()
-    # Result shape rho A[:-1] ++ rho B[1:]; the library validates the operands.
-    rs = tuple(a.shape[:-1]) + tuple(b.shape[1:])
+    rs = inner_shape(a.shape, b.shape)
     if out is None:
         out = torch.empty(rs, dtype=a.dtype, device=dev)
     else:
@@ -230,7 +248,7 @@ def outer(a: torch.Tensor, b: torch.Tensor, op: str = "mul", out: torch.Tensor |
     dev = _dev_operands(a, b)
     a = a.contiguous()
     b = b.contiguous()
-    rs = tuple(a.shape) + tuple(b.shape)  # rho A ++ rho B; the library validates
+    rs = outer_shape(a.shape, b.shape)
     if out is None:
         out = torch.empty(rs, dtype=a.dtype, device=dev)
     else:
@@ -252,8 +270,7 @@ def inner_split(a: torch.Tensor, b: torch.Tensor, fmt: str = "bf16", nslices: in
     dev = _dev_operands(a, b)
     a = a.contiguous()
     b = b.contiguous()
-    # Result shape rho A[:-1] ++ rho B[1:]; the library validates the operands.
-    rs = tuple(a.shape[:-1]) + tuple(b.shape[1:])
+    rs = inner_shape(a.shape, b.shape)
     if out is None:
         out = torch.empty(rs, dtype=torch.float64, device=dev)
     else:
@@ -294,23 +311,30 @@ def split_multiply(sa, sb, out: torch.Tensor, workspace: torch.Tensor, fmt: str 
                    stream=None):
     """Slice-pair products from `workspace` into `out` (second half of inner_split)."""
     dev = _dev_operands(out)
-    _check_out(out, tuple(sa[:-1]) + tuple(sb[1:]), torch.float64, dev)
+    _check_out(out, inner_shape(sa, sb), torch.float64, dev)
     _check_workspace(workspace, dev)
     st = stream if stream is not None else _stream(out.device)
     _check(lib().moa_inner_split_multiply(_shape(sa), _shape(sb), _ptr(out), SPLIT_FORMATS[fmt], nslices,
                                           ctypes.c_void_p(workspace.data_ptr()), _nbytes(workspace), st))
 
 
-def inner_grad(a, b, g, need_a=True, need_b=True):
-    """(dA, dB) of the (+,*) inner product for upstream gradient g."""
+def inner_grad(a, b, g, need_a=True, need_b=True, out_a=None, out_b=None):
+    """(dA, dB) of the (+,*) inner product for upstream gradient g.
+    out_a / out_b: optional caller-supplied result tensors (dense, A's and
+    B's shape and dtype, on their device)."""
     if not (a.dtype == b.dtype == g.dtype) or a.dtype not in (torch.float32, torch.float64):
         raise TypeError("inner_grad takes float32 or float64 operands")
     dev = _dev_operands(a, b, g)
     a, b, g = a.contiguous(), b.contiguous(), g.contiguous()
     if tuple(g.shape) != inner_shape(a.shape, b.shape):
         raise ValueError("g must have the result shape")
-    da = torch.empty_like(a) if need_a else None
-    db = torch.empty_like(b) if need_b else None
+    da = db = None
+    if need_a:
+        da = torch.empty_like(a) if out_a is None else out_a
+        _check_out(da, tuple(a.shape), a.dtype, dev)
+    if need_b:
+        db = torch.empty_like(b) if out_b is None else out_b
+        _check_out(db, tuple(b.shape), b.dtype, dev)
     _check(lib().moa_inner_grad(_shape(a.shape), _ptr(a), _shape(b.shape), _ptr(b), _ptr(g),
                                 _ptr(da) if da is not None else ctypes.c_void_p(0),
                                 _ptr(db) if db is not None else ctypes.c_void_p(0), DTYPES[a.dtype], _stream(dev)))
@@ -351,6 +375,7 @@ class Batch:
         dt = As[0].dtype if n else torch.float32
         if n:
             _dev_operands(*As, *Bs, *Ds)
+        self._check_results(As, Bs, Ds)
         self._shapes = []
         sa = (_Shape * max(1, n))()
         sb = (_Shape * max(1, n))()
@@ -371,6 +396,15 @@ class Batch:
         st = stream if stream is not None else _stream(As[0].device if n else None)
         _check(lib().moa_batch_build(n, sa, pa, sb, pb, pd, DTYPES[dt], st, ctypes.byref(h)))
         self._h = h
+
+    @staticmethod
+    def _check_results(As, Bs, Ds):
+        """The library writes the whole result of problem i from D[i]'s first
+        address, so each D[i] must have exactly that result's shape."""
+        for i, (a, b, d) in enumerate(zip(As, Bs, Ds)):
+            rs = inner_shape(a.shape, b.shape)
+            if tuple(d.shape) != rs:
+                raise ValueError("D[%d] has shape %s; problem %d's result has shape %s" % (i, tuple(d.shape), i, rs))
 
     def run(self, stream=None):
         st = stream if stream is not None else _stream()

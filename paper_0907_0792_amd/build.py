@@ -1,6 +1,7 @@
 """Build libmoa.so (HIP, gfx950) in-tree.
 
     python -m paper_0907_0792_amd.build      # or python paper_0907_0792_amd/build.py
+    python -m paper_0907_0792_amd.build --changed   # only units older than their sources
 
 Each ``csrc/*.hip`` file is compiled to an object with hipcc for gfx950 (in
 parallel), then linked into ``paper_0907_0792_amd/libmoa.so``. Packed FP32 VALU
@@ -30,8 +31,13 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _compile(src: str, verbose: bool, force: bool = True) -> str:
     obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
+    if not force and os.path.exists(obj):
+        # Up to date when newer than the source and every shared header.
+        deps = [src] + glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+        if os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps):
+            return obj
     cmd = [HIPCC] + CFLAGS + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -44,12 +50,14 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+def build(verbose: bool = False, jobs: int | None = None, force: bool = True) -> str:
+    """Compile every unit (force) or only those older than their sources
+    (force=False), then link."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        objs = list(ex.map(lambda s: _compile(s, verbose, force), srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
     # --no-undefined: a template instantiated in no unit fails here, not at load.
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp] + objs
@@ -63,5 +71,5 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, force="--changed" not in sys.argv)
     print("built", LIB)

@@ -39,8 +39,10 @@ __device__ __forceinline__ void grouped_tile(int64_t t, int64_t tiles_m, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Element operations of the generalized products. max/min follow
-// "a < b ? b : a" so an FP max of equal values keeps the left operand.
+// Element operations of the generalized products. int32 max/min are signed.
+// FP max/min are the IEEE 754-2019 maximum/minimum: a NaN operand gives NaN
+// and -0 orders below +0. That makes them associative and commutative bit for
+// bit (NaN payloads aside), so a fold over them has one value in any order.
 
 template <int OP, typename T>
 __device__ __forceinline__ T apply_op(T a, T b);
@@ -66,11 +68,17 @@ struct OpImpl<MOA_DIV, T> {
 };
 template <typename T>
 struct OpImpl<MOA_MAX, T> {
-  static __device__ __forceinline__ T f(T a, T b) { return (a < b) ? b : a; }
+  static __device__ __forceinline__ T f(T a, T b) {
+    if constexpr (T(1) / 2 == 0) return (a < b) ? b : a;
+    else return __builtin_elementwise_maximum(a, b);
+  }
 };
 template <typename T>
 struct OpImpl<MOA_MIN, T> {
-  static __device__ __forceinline__ T f(T a, T b) { return (b < a) ? b : a; }
+  static __device__ __forceinline__ T f(T a, T b) {
+    if constexpr (T(1) / 2 == 0) return (b < a) ? b : a;
+    else return __builtin_elementwise_minimum(a, b);
+  }
 };
 template <typename T>
 struct OpImpl<MOA_AND, T> {
@@ -103,9 +111,13 @@ __device__ __forceinline__ T apply_op(T a, T b) {
   return OpImpl<OP, T>::f(a, b);
 }
 
-// Identity of a fold op (value of an empty fold).
+// Identity of a fold op: the value a fold starts from. Folding every term
+// into it gives the left fold from the first term bit for bit, so for FP
+// addition it is -0 (-0 + x = x for every x, +0 and -0 included). An empty
+// fold gives +0 instead (launch_fill_identity).
 template <int OP, typename T>
 __device__ __forceinline__ T fold_identity() {
+  if constexpr (OP == MOA_ADD && T(1) / 2 != 0) return -T(0);
   if constexpr (OP == MOA_ADD || OP == MOA_OR || OP == MOA_XOR) return T(0);
   if constexpr (OP == MOA_MUL) return T(1);
   if constexpr (OP == MOA_AND) return T(-1);
@@ -121,8 +133,9 @@ __device__ __forceinline__ T fold_identity() {
 }
 
 // A fold op whose result does not depend on the association order in type T:
-// every int32 fold (wrapping + and * included) and FP max/min. Such folds may
-// combine two terms before folding them in.
+// every int32 fold (wrapping + and * included) and FP max/min (IEEE 754-2019
+// maximum/minimum, see above). Such folds may combine two terms before
+// folding them in.
 template <int OP, typename T>
 constexpr bool fold_reassociable() {
   if constexpr (T(1) / 2 == 0) return true;  // integer type

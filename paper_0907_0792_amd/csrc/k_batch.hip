@@ -205,12 +205,15 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
   hipStream_t cap = nullptr;
   if (n > 0 && (e = hipMalloc(&b->d_desc, sizeof(BatchDesc) * (size_t)n)) != hipSuccess) goto hip_error;
   if (!items.empty() && (e = hipMalloc(&b->d_items, sizeof(BatchItem) * items.size())) != hipSuccess) goto hip_error;
-  if (n > 0 &&
-      (e = hipMemcpy(b->d_desc, desc.data(), sizeof(BatchDesc) * (size_t)n, hipMemcpyHostToDevice)) != hipSuccess)
+  // The tables are uploaded on `stream` (ordered after the caller's earlier
+  // work there) and build waits for the copies, so the host vectors may go.
+  if (n > 0 && (e = hipMemcpyAsync(b->d_desc, desc.data(), sizeof(BatchDesc) * (size_t)n, hipMemcpyHostToDevice,
+                                   (hipStream_t)stream)) != hipSuccess)
     goto hip_error;
-  if (!items.empty() && (e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(),
-                                       hipMemcpyHostToDevice)) != hipSuccess)
+  if (!items.empty() && (e = hipMemcpyAsync(b->d_items, items.data(), sizeof(BatchItem) * items.size(),
+                                            hipMemcpyHostToDevice, (hipStream_t)stream)) != hipSuccess)
     goto hip_error;
+  if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) goto hip_error;
   // Capture the persistent launch on a private stream (capture is not allowed
   // on the legacy default stream); the graph is replayed on any stream.
   if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) goto hip_error;
@@ -271,24 +274,37 @@ moa_status moa_tile_table_get(char *buf, size_t len) {
   return MOA_OK;
 }
 
+// Bucket bit of one token: `hi` ("M>32") sets it, `lo` ("M<=32") clears it,
+// anything else is an error (-1).
+static int bucket_bit(const char *tok, const char *lo, const char *hi, int bit) {
+  if (strcmp(tok, hi) == 0) return bit;
+  if (strcmp(tok, lo) == 0) return 0;
+  return -1;
+}
+
 moa_status moa_tile_table_set(const char *text) {
   if (!text) return set_error(MOA_ERR_NULL, "text is NULL");
   int t[kBuckets];
-  int got = 0;
+  for (int bk = 0; bk < kBuckets; ++bk) t[bk] = -1;
   const char *p = text;
-  while (*p && got < kBuckets) {
+  while (*p == '\n' || *p == ' ' || *p == '\t') ++p;
+  while (*p) {
     char m[16], nn[16], k[16];
     int v, used = 0;
-    if (sscanf(p, "%15s %15s %15s %d%n", m, nn, k, &v, &used) != 4) break;
+    if (sscanf(p, "%15s %15s %15s %d%n", m, nn, k, &v, &used) != 4)
+      return set_error(MOA_ERR_ARG, "tile table line is not 'bucket_m bucket_n bucket_k variant'");
     if (v < 0 || v >= kVariants) return set_error(MOA_ERR_ARG, "tile variant out of range");
-    const int bk = (strcmp(m, "M>32") == 0 ? 4 : 0) + (strcmp(nn, "N>32") == 0 ? 2 : 0) +
-                   (strcmp(k, "K>128") == 0 ? 1 : 0);
+    const int bm = bucket_bit(m, "M<=32", "M>32", 4), bn = bucket_bit(nn, "N<=32", "N>32", 2),
+              bkk = bucket_bit(k, "K<=128", "K>128", 1);
+    if (bm < 0 || bn < 0 || bkk < 0) return set_error(MOA_ERR_ARG, "unknown bucket name in the tile table");
+    const int bk = bm + bn + bkk;
+    if (t[bk] >= 0) return set_error(MOA_ERR_ARG, "tile table sets a bucket twice");
     t[bk] = v;
-    ++got;
     p += used;
-    while (*p == '\n' || *p == ' ') ++p;
+    while (*p == '\n' || *p == ' ' || *p == '\t') ++p;
   }
-  if (got != kBuckets) return set_error(MOA_ERR_ARG, "tile table needs one line per bucket");
+  for (int bk = 0; bk < kBuckets; ++bk)
+    if (t[bk] < 0) return set_error(MOA_ERR_ARG, "tile table needs one line per bucket");
   std::lock_guard<std::mutex> lk(g_table_mu);
   memcpy(g_table, t, sizeof t);
   return MOA_OK;

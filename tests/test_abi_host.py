@@ -99,10 +99,10 @@ def test_inner_validation_before_launch():
     # D overlapping A (A spans 4*8*8 = 256 bytes).
     assert S[_call_inner(ok_a, A, ok_b, B, moa.OPS["add"], moa.OPS["mul"], 0, A + 128)] == "MOA_ERR_ALIAS"
     assert S[_call_inner(ok_a, A, ok_b, B, moa.OPS["add"], moa.OPS["mul"], 0, B - 8)] == "MOA_ERR_ALIAS"
+    assert "overlaps" in moa.lib().moa_last_error().decode()
     assert S[_call_inner(ok_a, A, ok_b, B, moa.OPS["add"], moa.OPS["mul"], 0, D, flags=8)] == "MOA_ERR_ARG"
     # Empty result: nothing to do, no launch, even with NULL pointers for empty arrays.
     assert S[_call_inner((0, 8), 0, ok_b, B, moa.OPS["add"], moa.OPS["mul"], 0, 0)] == "MOA_OK"
-    assert "overlaps" in moa.lib().moa_last_error().decode() or True
 
 
 def test_outer_validation():
@@ -167,6 +167,34 @@ def test_tile_table_roundtrip():
     assert moa.tile_table() == t
     with pytest.raises(moa.MoaError):
         moa.set_tile_table("M<=32 N<=32 K<=128 7\n")
+    # Unknown tokens, a bucket set twice, a missing bucket or a trailing
+    # malformed line are rejected, and the table stays as it was.
+    bad_token = flipped.replace("N>32", "N>=32", 1)
+    dup = "\n".join(lines[:7] + [lines[0]])
+    missing = "\n".join(lines[:7])
+    trailing = t + "M>32 N>32\n"
+    for text in (bad_token, dup, missing, trailing, ""):
+        with pytest.raises(moa.MoaError) as e:
+            moa.set_tile_table(text)
+        assert moa.STATUS[e.value.status] == "MOA_ERR_ARG"
+        assert moa.tile_table() == t
+    # Lines in any order are accepted.
+    moa.set_tile_table("\n".join(reversed(lines)) + "\n")
+    assert moa.tile_table() == t
+
+
+def test_binding_checks_batch_result_shapes():
+    # Each D[i] must hold exactly problem i's result: the library writes
+    # M * N elements from its first address (shapes checked before any launch;
+    # meta tensors carry shapes without memory).
+    import torch
+    a = torch.empty(4, 8, device="meta")
+    b = torch.empty(8, 3, device="meta")
+    with pytest.raises(ValueError):
+        moa.Batch._check_results([a], [b], [torch.empty(4, 2, device="meta")])
+    with pytest.raises(ValueError):
+        moa.Batch._check_results([a], [b], [torch.empty(3, 4, device="meta")])
+    moa.Batch._check_results([a], [b], [torch.empty(4, 3, device="meta")])
 
 
 def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):

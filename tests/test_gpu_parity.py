@@ -29,6 +29,104 @@ FOLD_I = ["add", "mul", "max", "min", "and", "or", "xor"]
 ELEM_I = ["add", "sub", "mul", "max", "min", "and", "or", "xor"]
 
 
+# ---------------------------------------------------------------------------
+# Every result (and every split workspace) the tests request lies between
+# sentinel bands of BAND bytes; after each call the bands must be intact, so
+# a store past either end of an output fails the test. The result itself is
+# pre-filled with 0xFF bytes (NaN for FP, -1 for int32), so an element a
+# kernel never writes shows up in the comparison.
+
+BAND = 4096
+SENTINEL = 0xA5
+UNWRITTEN = 0xFF
+
+
+class GuardPool:
+    """Buffers of the given (shape, dtype) laid out in one allocation, each
+    with BAND sentinel bytes before and after it (offsets 256-byte aligned)."""
+
+    def __init__(self, specs, fill=UNWRITTEN):
+        offs, pos = [], BAND
+        sizes = []
+        for shape, dtype in specs:
+            nb = math.prod(tuple(int(d) for d in shape)) * torch.empty((), dtype=dtype).element_size()
+            offs.append(pos)
+            sizes.append(nb)
+            pos += (nb + 255) // 256 * 256 + BAND
+        self.raw = torch.full((pos,), SENTINEL, dtype=torch.uint8, device=DEV)
+        self.t = []
+        # Byte ranges outside every buffer: the bands, plus each buffer's
+        # padding up to the next 256-byte boundary.
+        self.bands = []
+        prev = 0
+        for (shape, dtype), off, nb in zip(specs, offs, sizes):
+            self.raw[off:off + nb].fill_(fill)
+            self.t.append(self.raw[off:off + nb].view(dtype).view(tuple(int(d) for d in shape)))
+            self.bands.append((prev, off))
+            prev = off + nb
+        self.bands.append((prev, pos))
+        idx = torch.cat([torch.arange(a, b, dtype=torch.int64) for a, b in self.bands])
+        self.idx = idx.to(DEV)
+
+    def check(self, what):
+        torch.cuda.synchronize()
+        bad = self.raw[self.idx] != SENTINEL
+        if bool(bad.any()):
+            first = int(self.idx[torch.nonzero(bad)[0, 0]])
+            raise AssertionError("%s wrote %d bytes outside its buffers (first at byte %d of %d)"
+                                 % (what, int(bad.sum()), first, self.raw.numel()))
+
+
+def guarded(shape, dtype, fill=UNWRITTEN):
+    p = GuardPool([(shape, dtype)], fill)
+    return p, p.t[0]
+
+
+class _Guarded:
+    """The binding's entry points with guarded results: same names and
+    arguments, every output between sentinel bands, bands checked after each
+    call (which also synchronises)."""
+
+    def inner_ex(self, a, b, op1="add", op2="mul", flags=0):
+        p, out = guarded(moa.inner_shape(a.shape, b.shape), a.dtype)
+        moa.inner_ex(a, b, op1, op2, flags, out=out)
+        p.check("inner %s . %s (%s, %s)" % (tuple(a.shape), tuple(b.shape), op1, op2))
+        return out
+
+    def inner(self, a, b, op1="add", op2="mul"):
+        return self.inner_ex(a, b, op1, op2, 0)
+
+    def outer(self, a, b, op="mul"):
+        p, out = guarded(moa.outer_shape(a.shape, b.shape), a.dtype)
+        moa.outer(a, b, op, out=out)
+        p.check("outer %s o %s (%s)" % (tuple(a.shape), tuple(b.shape), op))
+        return out
+
+    def inner_axes(self, a, b, axes=(-1, 0), op1="add", op2="mul", flags=0):
+        p, out = guarded(moa.inner_axes_shape(a.shape, axes[0], b.shape, axes[1]), a.dtype)
+        moa.inner_axes(a, b, axes, op1, op2, flags, out=out)
+        p.check("inner_axes %s . %s over %s" % (tuple(a.shape), tuple(b.shape), tuple(axes)))
+        return out
+
+    def inner_split(self, a, b, fmt="bf16", nslices=5):
+        nb = max(1, moa.split_workspace_bytes(a.shape, b.shape, fmt, nslices))
+        p = GuardPool([(moa.inner_shape(a.shape, b.shape), torch.float64), ((nb,), torch.uint8)])
+        p.t[1].fill_(0x3C)  # workspace contents on entry are ignored
+        moa.inner_split(a, b, fmt, nslices, workspace=p.t[1], out=p.t[0])
+        p.check("inner_split %s . %s (%s, S=%d)" % (tuple(a.shape), tuple(b.shape), fmt, nslices))
+        return p.t[0]
+
+    def inner_grad(self, a, b, g, need_a=True, need_b=True):
+        p = GuardPool([(a.shape, a.dtype), (b.shape, b.dtype)])
+        da, db = moa.inner_grad(a, b, g, need_a, need_b, out_a=p.t[0] if need_a else None,
+                                out_b=p.t[1] if need_b else None)
+        p.check("inner_grad %s . %s" % (tuple(a.shape), tuple(b.shape)))
+        return da, db
+
+
+G = _Guarded()
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
@@ -45,12 +143,16 @@ def host(t):
 
 
 def eq(x, y):
+    """Bit for bit (+0 and -0 differ); any NaN matches any NaN, since NaN
+    payloads are not specified."""
     x = np.asarray(x)
     y = np.asarray(y)
     assert x.shape == y.shape, (x.shape, y.shape)
+    assert x.dtype == y.dtype, (x.dtype, y.dtype)
     if x.dtype.kind == "f":
+        u = np.dtype("u%d" % x.dtype.itemsize)
         nan = np.isnan(x) & np.isnan(y)
-        bad = ~((x == y) | nan)
+        bad = ~((x.view(u) == y.view(u)) | nan)
         assert not bad.any(), "mismatch at %s: %r vs %r" % (np.argwhere(bad)[0], x[bad][0], y[bad][0])
     else:
         assert np.array_equal(x, y), "mismatch at %s" % (np.argwhere(x != y)[0],)
@@ -74,9 +176,9 @@ def test_worked_example():
     for dt in (np.float64, np.float32, np.int32):
         a = np.arange(6, dtype=dt).reshape(2, 3)
         b = np.arange(12, dtype=dt).reshape(3, 4)
-        eq(host(moa.inner(gpu(a), gpu(b))), np.array([[20, 23, 26, 29], [56, 68, 80, 92]], dtype=dt))
-        eq(host(moa.inner(gpu(a), gpu(b), "max", "add")), np.array([[10, 11, 12, 13], [13, 14, 15, 16]], dtype=dt))
-        eq(host(moa.outer(gpu(a), gpu(b), "mul")), oracle.outer(a, b, "mul"))
+        eq(host(G.inner(gpu(a), gpu(b))), np.array([[20, 23, 26, 29], [56, 68, 80, 92]], dtype=dt))
+        eq(host(G.inner(gpu(a), gpu(b), "max", "add")), np.array([[10, 11, 12, 13], [13, 14, 15, 16]], dtype=dt))
+        eq(host(G.outer(gpu(a), gpu(b), "mul")), oracle.outer(a, b, "mul"))
 
 
 SIMT_SHAPES = [
@@ -101,7 +203,7 @@ def test_simt_all_op_pairs_bit_exact(dt):
         for op1 in folds:
             for op2 in elems:
                 say("simt", np.dtype(dt).name, sa, sb, op1, op2)
-                d = moa.inner_ex(ga, gb, op1, op2, flags=moa.FLAG_SEQUENTIAL_FOLD)
+                d = G.inner_ex(ga, gb, op1, op2, flags=moa.FLAG_SEQUENTIAL_FOLD)
                 eq(host(d), oracle.inner(a, b, op1, op2, mode="native"))
 
 
@@ -114,11 +216,11 @@ def test_simt_tiles_and_tails(tile):
     b = mi.uniform_i32(rng, (K, N))
     for op1, op2 in (("max", "add"), ("min", "sub"), ("add", "mul"), ("xor", "and")):
         say("simt tile", tile, op1, op2)
-        eq(host(moa.inner(gpu(a), gpu(b), op1, op2)), oracle.inner(a, b, op1, op2))
+        eq(host(G.inner(gpu(a), gpu(b), op1, op2)), oracle.inner(a, b, op1, op2))
     af = rand(rng, (M, K), np.float32)
     bf = rand(rng, (K, N), np.float32)
     say("simt tile f32 (+,-)", tile)
-    eq(host(moa.inner(gpu(af), gpu(bf), "add", "sub")), oracle.inner(af, bf, "add", "sub", mode="native"))
+    eq(host(G.inner(gpu(af), gpu(bf), "add", "sub")), oracle.inner(af, bf, "add", "sub", mode="native"))
 
 
 @pytest.mark.parametrize("dt", [np.int32, np.float64, np.float32])
@@ -138,7 +240,7 @@ def test_simt_vector_staging_ragged_and_misaligned(dt):
             ref = oracle.inner(a, b, op1, op2, mode="native")
             for name, ga in (("aligned", gpu(a)), ("misaligned", av)):
                 say("simt staging", name, np.dtype(dt).name, M, K, N, op1, op2)
-                eq(host(moa.inner_ex(ga, gpu(b), op1, op2, flags=moa.FLAG_SEQUENTIAL_FOLD)), ref)
+                eq(host(G.inner_ex(ga, gpu(b), op1, op2, flags=moa.FLAG_SEQUENTIAL_FOLD)), ref)
 
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32, np.int32])
@@ -155,7 +257,7 @@ def test_few_rows_stream_all_pairs_bit_exact(dt):
         for op1 in folds:
             for op2 in elems:
                 say("few rows", np.dtype(dt).name, M, K, N, op1, op2)
-                eq(host(moa.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
+                eq(host(G.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
 
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32, np.int32])
@@ -174,7 +276,7 @@ def test_few_rows_wide_runs_ragged(dt):
         for op1, op2 in ([("add", "mul"), ("max", "add"), ("xor", "and")] if dt == np.int32 else
                          [("add", "mul"), ("max", "add"), ("min", "div")]):
             say("few rows wide", np.dtype(dt).name, M, K, N, op1, op2)
-            eq(host(moa.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
+            eq(host(G.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
 
 
 @pytest.mark.parametrize("dt", [np.int32, np.float64, np.float32])
@@ -191,7 +293,7 @@ def test_few_columns_wave_reduction_bit_exact(dt):
         for op1 in folds:
             for op2 in elems:
                 say("few columns", np.dtype(dt).name, M, K, N, op1, op2)
-                eq(host(moa.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
+                eq(host(G.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
 
 
 @pytest.mark.parametrize("dt", [np.int32, np.float64])
@@ -208,14 +310,14 @@ def test_few_columns_misaligned_rows(dt):
     assert av.data_ptr() % 16 != 0
     op1 = "xor" if dt == np.int32 else "max"
     say("few columns misaligned", np.dtype(dt).name, op1)
-    eq(host(moa.inner(av, gpu(b), op1, "add")), oracle.inner(a, b, op1, "add", mode="native"))
+    eq(host(G.inner(av, gpu(b), op1, "add")), oracle.inner(a, b, op1, "add", mode="native"))
 
 
 def test_few_columns_workload_sampled():
     # int32 (max,+) <65536 4096> . <4096 8>: rows checked against the oracle.
     a, b = mi.workload_fewcols()
     say("few columns 65536 x 4096 . 4096 x 8")
-    d = host(moa.inner(gpu(a), gpu(b), "max", "add"))
+    d = host(G.inner(gpu(a), gpu(b), "max", "add"))
     rows = np.sort(np.random.default_rng(112).choice(a.shape[0], 64, replace=False))
     eq(d[rows], oracle.inner(a, b, "max", "add", rows=rows))
 
@@ -224,7 +326,7 @@ def test_few_rows_paper_workload_full():
     # Section II.B: A m x 128 (m = 4), B 128 x n, n = 2^22; every row checked.
     a, b = mi.workload_skinny()
     say("few rows 4 x 128 . 128 x 2^22")
-    d = host(moa.inner(gpu(a), gpu(b)))
+    d = host(G.inner(gpu(a), gpu(b)))
     eq(d, oracle.inner(a, b))
     assert nerr(d, oracle.inner_dot2(a, b)) <= 1e-14
 
@@ -236,12 +338,12 @@ def test_empty_and_degenerate():
         folds = FOLD_I if dt == np.int32 else FOLD_F
         for op1 in folds:
             say("K=0", op1)
-            d = host(moa.inner(gpu(a), gpu(b), op1, "add"))
+            d = host(G.inner(gpu(a), gpu(b), op1, "add"))
             eq(d, np.full((3, 5), oracle.identity_of(op1, dt), dtype=dt))
-        assert moa.inner(gpu(np.zeros((0, 4), dt)), gpu(np.ones((4, 3), dt))).shape == (0, 3)
-    d = host(moa.inner_split(gpu(np.zeros((3, 0))), gpu(np.zeros((0, 2)))))
+        assert G.inner(gpu(np.zeros((0, 4), dt)), gpu(np.ones((4, 3), dt))).shape == (0, 3)
+    d = host(G.inner_split(gpu(np.zeros((3, 0))), gpu(np.zeros((0, 2)))))
     eq(d, np.zeros((3, 2)))
-    c = host(moa.outer(gpu(np.array(3.0)), gpu(np.array(4.0)), "sub"))
+    c = host(G.outer(gpu(np.array(3.0)), gpu(np.array(4.0)), "sub"))
     assert c.shape == () and c == -1.0
 
 
@@ -254,7 +356,7 @@ def test_outer_all_ops_bit_exact(dt):
         b = rand(rng, sb, dt)
         for op in elems:
             say("outer", np.dtype(dt).name, sa, sb, op)
-            eq(host(moa.outer(gpu(a), gpu(b), op)), oracle.outer(a, b, op))
+            eq(host(G.outer(gpu(a), gpu(b), op)), oracle.outer(a, b, op))
 
 
 @pytest.mark.parametrize("dt,tol", [(np.float64, 1e-13), (np.float32, 1e-5)])
@@ -265,7 +367,7 @@ def test_mfma_plus_times(dt, tol):
         a = mi.uniform_f64(rng, sa).astype(dt)
         b = mi.uniform_f64(rng, sb).astype(dt)
         say("mfma", np.dtype(dt).name, sa, sb)
-        d = host(moa.inner(gpu(a), gpu(b)))
+        d = host(G.inner(gpu(a), gpu(b)))
         ref = oracle.inner_dot2(a, b)
         assert nerr(d, ref) <= tol, nerr(d, ref)
 
@@ -281,7 +383,7 @@ def test_mfma_vector_panels_ragged_and_misaligned(dt, tol):
         b = mi.uniform_f64(rng, sb).astype(dt)
         ref = oracle.inner_dot2(a, b)
         say("mfma vector panels", np.dtype(dt).name, sa, sb)
-        assert nerr(host(moa.inner(gpu(a), gpu(b))), ref) <= tol
+        assert nerr(host(G.inner(gpu(a), gpu(b))), ref) <= tol
         ta = torch.zeros(a.size + 1, dtype=gpu(a).dtype, device=DEV)
         tb = torch.zeros(b.size + 1, dtype=gpu(b).dtype, device=DEV)
         ta[1:] = gpu(a.ravel())
@@ -289,7 +391,7 @@ def test_mfma_vector_panels_ragged_and_misaligned(dt, tol):
         av, bv = ta[1:].view(sa), tb[1:].view(sb)
         assert av.data_ptr() % 16 != 0 and bv.data_ptr() % 16 != 0
         say("mfma misaligned", np.dtype(dt).name, sa, sb)
-        assert nerr(host(moa.inner(av, bv)), ref) <= tol
+        assert nerr(host(G.inner(av, bv)), ref) <= tol
 
 
 def test_mfma_f32_large_tiles_transposed_operands():
@@ -300,7 +402,7 @@ def test_mfma_f32_large_tiles_transposed_operands():
     for sb, ax_b in (((64, 3000), 0), ((3000, 64), 1)):
         b = mi.uniform_f64(rng, sb).astype(np.float32)
         say("mfma f32 large tiles, axes", (0, ax_b))
-        got = host(moa.inner_axes(gpu(a), gpu(b), (0, ax_b)))
+        got = host(G.inner_axes(gpu(a), gpu(b), (0, ax_b)))
         am, bm = _moved(a, 0, b, ax_b)
         rows = np.sort(rng.choice(3000, 20, replace=False))
         ref = oracle.inner_dot2(np.ascontiguousarray(am), np.ascontiguousarray(bm), rows=rows)
@@ -314,7 +416,7 @@ def test_mfma_f64_exact_integers():
     a = mi.small_int_f64(rng, (200, 1000), 8)
     b = mi.small_int_f64(rng, (1000, 130), 8)
     say("mfma exact ints")
-    eq(host(moa.inner(gpu(a), gpu(b))), (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
+    eq(host(G.inner(gpu(a), gpu(b))), (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
 
 
 # ---------------------------------------------------------------------------
@@ -328,16 +430,16 @@ def _sample_rows(rng, m, n=24):
 def test_small_mixed_full():
     a, b, oa, ob = mi.workload_small_mixed()
     say("512^3 fp64 + outer 32x32 o 16x16")
-    d = host(moa.inner(gpu(a), gpu(b)))
+    d = host(G.inner(gpu(a), gpu(b)))
     assert nerr(d, oracle.inner_dot2(a, b)) <= 1e-13
-    eq(host(moa.outer(gpu(oa), gpu(ob), "mul")), oracle.outer(oa, ob, "mul"))
+    eq(host(G.outer(gpu(oa), gpu(ob), "mul")), oracle.outer(oa, ob, "mul"))
 
 
 def test_rank_general_fp64_full_sampled():
     a, b = mi.workload_rank_general_f64()
     say("rank-5 fp64", a.shape, b.shape)
     ga, gb = gpu(a), gpu(b)
-    d = moa.inner(ga, gb)
+    d = G.inner(ga, gb)
     assert tuple(d.shape) == (64, 64, 32, 128, 64)
     m = 64 * 64 * 32
     rows = _sample_rows(np.random.default_rng(5), m)
@@ -352,7 +454,7 @@ def test_rank_general_fp64_full_sampled():
 def test_tropical_full_sampled():
     a, b = mi.workload_tropical()
     say("tropical 2048^3 (max,+)")
-    d = moa.inner(gpu(a), gpu(b), "max", "add")
+    d = G.inner(gpu(a), gpu(b), "max", "add")
     rows = _sample_rows(np.random.default_rng(6), 2048, 64)
     got = host(d[torch.from_numpy(rows).to(DEV)])
     eq(got, oracle.inner(a, b, "max", "add", rows=rows))
@@ -361,7 +463,7 @@ def test_tropical_full_sampled():
 def test_outer_f32_full_sampled():
     a, b = mi.workload_outer_f32()
     say("outer fp32 (-) <512 512> o <64 64>")
-    c = moa.outer(gpu(a), gpu(b), "sub")
+    c = G.outer(gpu(a), gpu(b), "sub")
     assert tuple(c.shape) == (512, 512, 64, 64)
     rows = _sample_rows(np.random.default_rng(7), 512 * 512, 64)
     got = host(c.reshape(512 * 512, -1)[torch.from_numpy(rows).to(DEV)])
@@ -382,7 +484,7 @@ def test_split_matches_oracle_scheme(shape):
     ref = oracle.inner_dot2(a, b)
     for S in range(1, 8):
         say("split", shape, "S", S)
-        d = host(moa.inner_split(gpu(a), gpu(b), "bf16", S))
+        d = host(G.inner_split(gpu(a), gpu(b), "bf16", S))
         want = oracle.split_inner(a, b, nslices=S, beta=9)
         assert nerr(d, want) <= 1e-14, (S, nerr(d, want))
         if S >= 5:
@@ -398,15 +500,15 @@ def test_split_exact_cases():
     a[:, 0] = 200.0
     b[0, :] = -200.0
     say("split exact integers")
-    d = host(moa.inner_split(gpu(a), gpu(b), "bf16", 1))
+    d = host(G.inner_split(gpu(a), gpu(b), "bf16", 1))
     eq(d, (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
     # Power-of-two row/column scaling commutes exactly with the scheme.
     a = mi.scaled_f64(rng, (40, 300))
     b = mi.scaled_f64(rng, (300, 50))
-    d = host(moa.inner_split(gpu(a), gpu(b), "bf16", 5))
+    d = host(G.inner_split(gpu(a), gpu(b), "bf16", 5))
     a2 = a.copy()
     a2[7] = np.ldexp(a2[7], 11)
-    d2 = host(moa.inner_split(gpu(a2), gpu(b), "bf16", 5))
+    d2 = host(G.inner_split(gpu(a2), gpu(b), "bf16", 5))
     want = d.copy()
     want[7] = np.ldexp(want[7], 11)
     eq(d2, want)
@@ -415,7 +517,7 @@ def test_split_exact_cases():
 def test_split_full_size_sampled():
     a, b = mi.workload_split()
     say("split 8192^3 S=5")
-    d = moa.inner_split(gpu(a), gpu(b), "bf16", 5)
+    d = G.inner_split(gpu(a), gpu(b), "bf16", 5)
     rows = _sample_rows(np.random.default_rng(8), 8192, 14)
     got = host(d[torch.from_numpy(rows).to(DEV)])
     ref = oracle.inner_dot2(a, b, rows=rows)
@@ -441,7 +543,7 @@ def test_split_int8_matches_oracle_scheme(shape):
     ref = oracle.inner_dot2(a, b)
     for S in range(1, 8):
         say("split int8", shape, "S", S)
-        d = host(moa.inner_split(gpu(a), gpu(b), "int8", S))
+        d = host(G.inner_split(gpu(a), gpu(b), "int8", S))
         want = oracle.split_inner(a, b, nslices=S, beta=7)
         assert nerr(d, want) <= 1e-14, (S, nerr(d, want))
         if S == 7:
@@ -457,14 +559,14 @@ def test_split_int8_exact_integers():
     a[:, 3] = 40.0
     b[5, :] = -50.0
     say("split int8 exact integers")
-    d = host(moa.inner_split(gpu(a), gpu(b), "int8", 1))
+    d = host(G.inner_split(gpu(a), gpu(b), "int8", 1))
     eq(d, (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
 
 
 def test_split_int8_full_size_sampled():
     a, b = mi.workload_split()
     say("split int8 8192^3 S=7")
-    d = moa.inner_split(gpu(a), gpu(b), "int8", 7)
+    d = G.inner_split(gpu(a), gpu(b), "int8", 7)
     rows = _sample_rows(np.random.default_rng(9), 8192, 10)
     got = host(d[torch.from_numpy(rows).to(DEV)])
     ref = oracle.inner_dot2(a, b, rows=rows)
@@ -488,13 +590,13 @@ def test_grad_finite_differences_fp64():
     b = mi.uniform_f64(rng, (8, 4, 4))
     g = mi.uniform_f64(rng, (4, 4, 4, 4))
     say("grad FD 4x4x8 . 8x4x4")
-    da, db = moa.inner_grad(gpu(a), gpu(b), gpu(g))
+    da, db = G.inner_grad(gpu(a), gpu(b), gpu(g))
     da, db = host(da), host(db)
     gb, gg = gpu(b), gpu(g)
     h = 2.0 ** -8
 
     def loss(x, y):
-        return float(torch.sum(moa.inner(gpu(x), gpu(y)) * gg).item())
+        return float(torch.sum(G.inner(gpu(x), gpu(y)) * gg).item())
 
     fa = np.zeros_like(a)
     for idx in np.ndindex(a.shape):
@@ -545,7 +647,7 @@ def test_grad_shapes_paired_and_separate(dt, tol):
         b = mi.uniform_f64(rng, (K, N)).astype(dt)
         g = mi.uniform_f64(rng, (M, N)).astype(dt)
         say("grad", np.dtype(dt).name, M, K, N)
-        da, db = moa.inner_grad(gpu(a), gpu(b), gpu(g))
+        da, db = G.inner_grad(gpu(a), gpu(b), gpu(g))
         rows = None if M <= 4100 else np.sort(rng.choice(M, 16, replace=False))
         ref_da = oracle.inner_dot2(g, np.ascontiguousarray(b.T), rows=rows)
         got_da = host(da) if rows is None else host(da)[rows]
@@ -554,9 +656,9 @@ def test_grad_shapes_paired_and_separate(dt, tol):
     a = mi.uniform_f64(rng, (70, 40)).astype(dt)
     b = mi.uniform_f64(rng, (40, 90)).astype(dt)
     g = mi.uniform_f64(rng, (70, 90)).astype(dt)
-    da, db = moa.inner_grad(gpu(a), gpu(b), gpu(g), need_a=True, need_b=False)
+    da, db = G.inner_grad(gpu(a), gpu(b), gpu(g), need_a=True, need_b=False)
     assert db is None and nerr(host(da), oracle.inner_dot2(g, np.ascontiguousarray(b.T))) <= tol
-    da, db = moa.inner_grad(gpu(a), gpu(b), gpu(g), need_a=False, need_b=True)
+    da, db = G.inner_grad(gpu(a), gpu(b), gpu(g), need_a=False, need_b=True)
     assert da is None and nerr(host(db), oracle.inner_dot2(np.ascontiguousarray(a.T), g)) <= tol
 
 
@@ -576,7 +678,8 @@ def test_batch_small_full_check():
     probs = mi.batch_problems(mi.rng_for(mi.BATCH, salt=1), 600)
     As = [gpu(p.a) for p in probs]
     Bs = [gpu(p.b) for p in probs]
-    Ds = [torch.full(moa.inner_shape(p.shape_a, p.shape_b), float("nan"), device=DEV) for p in probs]
+    pool = GuardPool([(moa.inner_shape(p.shape_a, p.shape_b), torch.float32) for p in probs])
+    Ds = pool.t
     say("batch 600")
     bt = moa.Batch(As, Bs, Ds)
     items, launches = bt.info()
@@ -585,7 +688,7 @@ def test_batch_small_full_check():
         for d in Ds:
             d.fill_(float("nan"))
         bt.run()
-        torch.cuda.synchronize()
+        pool.check("batch of 600, run %d" % rep)
         hd = [d.cpu().numpy() for d in Ds]
         _check_batch(probs, hd, range(len(probs)))
     bt.close()
@@ -599,10 +702,12 @@ def test_batch_wide_problem_64bit_offsets():
     a_s = [rng.integers(-2, 3, size=sa).astype(np.float32) for sa, _ in shapes]
     b_s = [rng.integers(-2, 3, size=sb).astype(np.float32) for _, sb in shapes]
     As, Bs = [gpu(a) for a in a_s], [gpu(b) for b in b_s]
-    Ds = [torch.full((sa[0], sb[1]), float("nan"), device=DEV) for sa, sb in shapes]
+    pool = GuardPool([((sa[0], sb[1]), torch.float32) for sa, sb in shapes])
+    Ds = pool.t
     say("batch with a 2 x 3 . 3 x 32.1M problem")
     bt = moa.Batch(As, Bs, Ds)
     bt.run()
+    pool.check("batch with 64-bit offsets")
     for a, b, d in zip(a_s, b_s, Ds):
         eq(host(d), (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float32))
     bt.close()
@@ -614,12 +719,13 @@ def test_batch_full_size_sampled():
     probs = mi.batch_problems(mi.rng_for(mi.BATCH), 10000)
     As = [gpu(p.a) for p in probs]
     Bs = [gpu(p.b) for p in probs]
-    Ds = [torch.empty(moa.inner_shape(p.shape_a, p.shape_b), device=DEV) for p in probs]
+    pool = GuardPool([(moa.inner_shape(p.shape_a, p.shape_b), torch.float32) for p in probs])
+    Ds = pool.t
     say("batch 10000")
     bt = moa.Batch(As, Bs, Ds)
     bt.run()
     bt.run()
-    torch.cuda.synchronize()
+    pool.check("batch of 10000")
     idx = np.random.default_rng(9).choice(len(probs), 400, replace=False)
     _check_batch(probs, {int(i): Ds[int(i)].cpu().numpy() for i in idx}, [int(i) for i in idx])
     bt.close()
@@ -632,10 +738,11 @@ def test_batch_autotune_then_build():
     probs = mi.batch_problems(mi.rng_for(mi.BATCH, salt=2), 200)
     As = [gpu(p.a) for p in probs]
     Bs = [gpu(p.b) for p in probs]
-    Ds = [torch.empty(moa.inner_shape(p.shape_a, p.shape_b), device=DEV) for p in probs]
+    pool = GuardPool([(moa.inner_shape(p.shape_a, p.shape_b), torch.float32) for p in probs])
+    Ds = pool.t
     bt = moa.Batch(As, Bs, Ds)
     bt.run()
-    torch.cuda.synchronize()
+    pool.check("autotuned batch")
     _check_batch(probs, [d.cpu().numpy() for d in Ds], range(len(probs)))
     bt.close()
 
@@ -706,7 +813,7 @@ def test_inner_axes_all_pairs_bit_exact(dt):
         ga, gb = gpu(a), gpu(b)
         for op1 in folds:
             for op2 in elems:
-                got = host(moa.inner_axes(ga, gb, (ax_a, ax_b), op1, op2, flags=moa.FLAG_SEQUENTIAL_FOLD))
+                got = host(G.inner_axes(ga, gb, (ax_a, ax_b), op1, op2, flags=moa.FLAG_SEQUENTIAL_FOLD))
                 eq(got, oracle.inner_axes(a, ax_a, b, ax_b, op1, op2, mode="native"))
 
 
@@ -716,7 +823,7 @@ def test_inner_axes_mfma(dt, tol):
     for sa, ax_a, sb, ax_b in AXES_CASES:
         say("axes (+,*)", dt.__name__, sa, ax_a, sb, ax_b)
         a, b = rand(rng, sa, dt), rand(rng, sb, dt)
-        got = host(moa.inner_axes(gpu(a), gpu(b), (ax_a, ax_b)))
+        got = host(G.inner_axes(gpu(a), gpu(b), (ax_a, ax_b)))
         ref = oracle.inner_dot2(*_moved(a.astype(np.float64), ax_a, b.astype(np.float64), ax_b))
         assert got.shape == ref.shape
         assert nerr(got, ref) <= tol
@@ -729,15 +836,15 @@ def test_inner_axes_mfma_exact_integers():
     for sa, ax_a, sb, ax_b in AXES_CASES:
         a = mi.small_int_f64(rng, sa, 8)
         b = mi.small_int_f64(rng, sb, 8)
-        eq(host(moa.inner_axes(gpu(a), gpu(b), (ax_a, ax_b))), oracle.inner_axes(a, ax_a, b, ax_b))
+        eq(host(G.inner_axes(gpu(a), gpu(b), (ax_a, ax_b))), oracle.inner_axes(a, ax_a, b, ax_b))
 
 
 def test_inner_axes_last_with_first_equals_inner():
     rng = np.random.default_rng(44)
     a, b = rand(rng, (40, 9, 33), np.float64), rand(rng, (33, 70), np.float64)
     ga, gb = gpu(a), gpu(b)
-    eq(host(moa.inner_axes(ga, gb, (-1, 0))), host(moa.inner(ga, gb)))
-    eq(host(moa.inner_axes(ga, gb, (2, 0), "max", "add")), host(moa.inner(ga, gb, "max", "add")))
+    eq(host(G.inner_axes(ga, gb, (-1, 0))), host(G.inner(ga, gb)))
+    eq(host(G.inner_axes(ga, gb, (2, 0), "max", "add")), host(G.inner(ga, gb, "max", "add")))
 
 
 def test_inner_axes_large_sampled():
@@ -745,13 +852,13 @@ def test_inner_axes_large_sampled():
     rng = np.random.default_rng(45)
     a = mi.uniform_f64(rng, (64, 512, 48))
     b = mi.uniform_f64(rng, (32, 512, 40))
-    got = host(moa.inner_axes(gpu(a), gpu(b), (1, 1))).reshape(3072, 1280)
+    got = host(G.inner_axes(gpu(a), gpu(b), (1, 1))).reshape(3072, 1280)
     am, bm = _moved(a, 1, b, 1)
     rows = np.sort(rng.choice(3072, 24, replace=False))
     ref = oracle.inner_dot2(am, bm, rows=rows).reshape(len(rows), 1280)
     assert nerr(got[rows], ref) <= 1e-13
     at, bt = rand(rng, (300, 64, 7), np.int32), rand(rng, (9, 64, 150), np.int32)
-    got = host(moa.inner_axes(gpu(at), gpu(bt), (1, 1), "max", "add")).reshape(2100, 1350)
+    got = host(G.inner_axes(gpu(at), gpu(bt), (1, 1), "max", "add")).reshape(2100, 1350)
     rows = np.sort(rng.choice(2100, 24, replace=False))
     ref = oracle.inner_axes(at, 1, bt, 1, "max", "add", rows=rows).reshape(len(rows), 1350)
     eq(got[rows], ref)
@@ -769,7 +876,7 @@ def test_split_two_stage_api_matches_one_call():
     ga, gb = gpu(a), gpu(b)
     for fmt, S, beta in (("bf16", 5, 9), ("int8", 7, 7)):
         say("split two-stage", fmt)
-        one = host(moa.inner_split(ga, gb, fmt, S))
+        one = host(G.inner_split(ga, gb, fmt, S))
         ws = torch.empty(moa.split_workspace_bytes(a.shape, b.shape, fmt, S), dtype=torch.uint8, device=DEV)
         out = torch.full((200, 150), float("nan"), dtype=torch.float64, device=DEV)
         moa.split_prepare(ga, gb, ws, fmt, S)
@@ -789,12 +896,12 @@ def test_batch_fp64():
     probs = [(sa, sb, mi.uniform_f64(rng, sa), mi.uniform_f64(rng, sb)) for sa, sb in shapes]
     As = [gpu(a) for _, _, a, _ in probs]
     Bs = [gpu(b) for _, _, _, b in probs]
-    Ds = [torch.full(moa.inner_shape(sa, sb), float("nan"), dtype=torch.float64, device=DEV)
-          for sa, sb, _, _ in probs]
+    pool = GuardPool([(moa.inner_shape(sa, sb), torch.float64) for sa, sb, _, _ in probs])
+    Ds = pool.t
     say("batch fp64 300")
     bt = moa.Batch(As, Bs, Ds)
     bt.run()
-    torch.cuda.synchronize()
+    pool.check("batch fp64")
     for (sa, sb, a, b), d in zip(probs, Ds):
         assert nerr(d.cpu().numpy(), oracle.inner_dot2(a, b)) <= 1e-13, (sa, sb)
     bt.close()
@@ -809,8 +916,8 @@ def test_non_default_stream():
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         ga, gb = gpu(a), gpu(b)
-        d = moa.inner(ga, gb, "max", "add")
-        c = moa.outer(ga[:3], gb[0], "sub")
+        d = G.inner(ga, gb, "max", "add")
+        c = G.outer(ga[:3], gb[0], "sub")
     s.synchronize()
     eq(d.cpu().numpy(), oracle.inner(a, b, "max", "add"))
     eq(c.cpu().numpy(), oracle.outer(a[:3], b[0], "sub"))
@@ -830,10 +937,10 @@ def test_int32_wraparound_every_path():
         ga, gb = gpu(a), gpu(b)
         for op1, op2 in [("add", "mul"), ("mul", "add"), ("add", "sub"), ("max", "mul"), ("xor", "mul")]:
             say("int32 wrap", sa, sb, op1, op2)
-            eq(host(moa.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2))
+            eq(host(G.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2))
     a, b = big((33, 17)), big((9, 129))
     for op in ("add", "sub", "mul"):
-        eq(host(moa.outer(gpu(a), gpu(b), op)), oracle.outer(a, b, op))
+        eq(host(G.outer(gpu(a), gpu(b), op)), oracle.outer(a, b, op))
 
 
 def test_maximum_rank_and_unit_axes():
@@ -842,21 +949,21 @@ def test_maximum_rank_and_unit_axes():
     sb = (5, 1, 1, 1, 1, 1, 1, 1, 2, 1, 1, 1, 1, 1, 1, 3)          # rank 16
     a = rand(rng, sa, np.int32)
     b = rand(rng, sb, np.int32)
-    d = host(moa.inner(gpu(a), gpu(b), "add", "mul"))
+    d = host(G.inner(gpu(a), gpu(b), "add", "mul"))
     assert d.shape == sa[:-1] + sb[1:]
     eq(d, oracle.inner(a, b, "add", "mul"))
     with pytest.raises(moa.MoaError):
         moa.inner(gpu(np.zeros((1,) * 17, np.int32)), gpu(np.zeros((1, 1), np.int32)))
     x = rand(rng, (1, 1, 4), np.float64)
     y = rand(rng, (4, 1, 1), np.float64)
-    eq(host(moa.inner(gpu(x), gpu(y), "max", "sub")), oracle.inner(x, y, "max", "sub", mode="native"))
+    eq(host(G.inner(gpu(x), gpu(y), "max", "sub")), oracle.inner(x, y, "max", "sub", mode="native"))
 
 
 def test_plain_fp64_8192_sampled():
     # The plain FP64 comparator of the split benchmark, at its full size.
     a, b = mi.workload_split()
     say("plain fp64 8192^3")
-    d = host(moa.inner(gpu(a), gpu(b)))
+    d = host(G.inner(gpu(a), gpu(b)))
     rows = np.sort(np.random.default_rng(140).choice(8192, 12, replace=False))
     ref = oracle.inner_dot2(a, b, rows=rows)
     assert nerr(d[rows], ref) <= 1e-13
@@ -872,8 +979,238 @@ def test_axes_bench_config_sampled():
     # <16 2048 512> . <16 2048 512> over axes (1, 1), as benchmarked.
     a, b = mi.workload_axes()
     say("axes <16 2048 512> . <16 2048 512>")
-    d = host(moa.inner_axes(gpu(a), gpu(b), (1, 1))).reshape(8192, 8192)
+    d = host(G.inner_axes(gpu(a), gpu(b), (1, 1))).reshape(8192, 8192)
     am, bm = np.moveaxis(a, 1, -1), np.moveaxis(b, 1, 0)
     rows = np.sort(np.random.default_rng(141).choice(8192, 12, replace=False))
     ref = oracle.inner_dot2(am, bm, rows=rows).reshape(len(rows), 8192)
     assert nerr(d[rows], ref) <= 1e-13
+
+
+
+# ---------------------------------------------------------------------------
+# Exact FP32 cases for every matrix-core kernel variant: small integer
+# entries (|x| <= 8) keep every partial sum an exact FP32 integer (below
+# 2^24), so any summation order gives the exact product, element by element.
+
+def _ints32(rng, shape):
+    return mi.small_int_f64(rng, shape, 8).astype(np.float32)
+
+
+def _exact_tensordot(a, ax_a, b, ax_b):
+    return np.tensordot(a.astype(np.float64), b.astype(np.float64), axes=([ax_a], [ax_b])).astype(np.float32)
+
+
+FP32_GEMM_VARIANTS = [
+    # (shape A, axis, shape B, axis, what the dispatch picks)
+    ((200, 50), 1, (50, 130), 0, "32x32 tiles, scalar panels"),
+    ((200, 52), 1, (52, 132), 0, "32x32 tiles, vector panels"),
+    ((1100, 36), 1, (36, 1000), 0, "64x64 tiles, vector panels"),
+    ((1100, 37), 1, (37, 1001), 0, "64x64 tiles, scalar panels"),
+    ((3000, 64), 1, (64, 3000), 0, "128x128 tiles, 32-bit index kernel"),
+    ((3000, 65), 1, (65, 3001), 0, "128x128 tiles, 64-bit index, scalar panels"),
+    ((64, 3000), 0, (64, 3000), 0, "A stored K x M (TA), 128x128, 32-bit index"),
+    ((3000, 64), 1, (3000, 64), 1, "B stored N x K (TB), 128x128, 32-bit index"),
+    ((64, 3000), 0, (3000, 64), 1, "TA and TB, 128x128, 32-bit index"),
+    ((45, 150), 0, (130, 45), 1, "TA and TB, 32x32"),
+    ((7, 45, 33), 1, (20, 45, 13), 1, "strided views (GEN), scalar"),
+    ((5, 36, 8), 1, (12, 36, 20), 1, "strided views (GEN), vector panels"),
+    ((3, 2, 70), 2, (70, 5, 9), 0, "rank 3 . rank 3"),
+]
+
+
+@pytest.mark.parametrize("case", FP32_GEMM_VARIANTS, ids=[c[4] for c in FP32_GEMM_VARIANTS])
+def test_fp32_gemm_variants_exact_integers(case):
+    sa, ax_a, sb, ax_b, what = case
+    rng = np.random.default_rng(160)
+    a, b = _ints32(rng, sa), _ints32(rng, sb)
+    say("fp32 exact", what, sa, ax_a, sb, ax_b)
+    got = host(G.inner_axes(gpu(a), gpu(b), (ax_a, ax_b)))
+    eq(got, _exact_tensordot(a, ax_a, b, ax_b))
+
+
+@pytest.mark.parametrize("M,K,N", [(300, 70, 130), (1030, 260, 900), (4096, 512, 4096), (3000, 3000, 3000)])
+def test_fp32_grad_exact_integers(M, K, N):
+    # Paired gradient launches (32x32, 64x64 and the workload's 64x64
+    # vector kernel) and the 128x128 pair, element by element.
+    rng = np.random.default_rng(161)
+    a, b, g = _ints32(rng, (M, K)), _ints32(rng, (K, N)), _ints32(rng, (M, N))
+    say("fp32 grad exact", M, K, N)
+    da, db = G.inner_grad(gpu(a), gpu(b), gpu(g))
+    ra = np.sort(rng.choice(M, min(M, 64), replace=False))
+    rb = np.sort(rng.choice(K, min(K, 64), replace=False))
+    g64, b64, a64 = g.astype(np.float64), b.astype(np.float64), a.astype(np.float64)
+    eq(host(da)[ra], (g64[ra] @ b64.T).astype(np.float32))
+    eq(host(db)[rb], (a64.T[rb] @ g64).astype(np.float32))
+
+
+def test_fp32_batch_exact_integers_32bit_index():
+    # The production batch kernel (32-bit tile offsets, both tile variants via
+    # the table) on the batch workload's shape distribution, every problem
+    # compared element by element.
+    rng = np.random.default_rng(162)
+    shapes = mi.batch_shapes(rng, 800)
+    a_s = [_ints32(rng, sa) for sa, _ in shapes]
+    b_s = [_ints32(rng, sb) for _, sb in shapes]
+    saved = moa.tile_table()
+    try:
+        for variant in (0, 1):
+            table = "\n".join(" ".join(l.split()[:3] + [str(variant)]) for l in saved.strip().splitlines())
+            moa.set_tile_table(table)
+            pool = GuardPool([(moa.inner_shape(sa, sb), torch.float32) for sa, sb in shapes])
+            say("batch exact, tile variant", variant)
+            bt = moa.Batch([gpu(a) for a in a_s], [gpu(b) for b in b_s], pool.t)
+            bt.run()
+            pool.check("exact batch, variant %d" % variant)
+            for a, b, d in zip(a_s, b_s, pool.t):
+                eq(host(d), _exact_tensordot(a, a.ndim - 1, b, 0))
+            bt.close()
+    finally:
+        moa.set_tile_table(saved)
+
+
+# ---------------------------------------------------------------------------
+# Split products with K past 8192: the INT8 kernel folds its INT32 levels into
+# FP64 in the middle of the loop (every 8192 k), the BF16 kernel runs a
+# 64-k tail after its unrolled 256-k cycles.
+
+@pytest.mark.parametrize("fmt,S,beta", [("bf16", 5, 9), ("int8", 7, 7)])
+def test_split_contraction_longer_than_8192(fmt, S, beta):
+    rng = np.random.default_rng(163)
+    a = mi.scaled_f64(rng, (200, 12000))
+    b = mi.scaled_f64(rng, (12000, 150))
+    say("split", fmt, "200 x 12000 . 12000 x 150")
+    d = host(G.inner_split(gpu(a), gpu(b), fmt, S))
+    rows = np.sort(np.concatenate([[0, 199], rng.choice(np.arange(1, 199), 14, replace=False)]))
+    want = oracle.split_inner(a, b, nslices=S, beta=beta, rows=rows)
+    assert nerr(d[rows], want) <= 1e-14, nerr(d[rows], want)
+    ref = oracle.inner_dot2(a, b, rows=rows)
+    assert nerr(d[rows], ref) <= 1e-12, nerr(d[rows], ref)
+
+
+# ---------------------------------------------------------------------------
+# Differentiation through torch.autograd: MoaInner.apply forward, the
+# hand-written backward through torch.autograd.grad, against FP64 central
+# differences (L = <G, D> is linear in each element, so they are exact up to
+# rounding).
+
+def test_grad_finite_differences_through_autograd():
+    rng = mi.rng_for(mi.DIFFERENTIATION, salt=1)
+    a = mi.uniform_f64(rng, (4, 4, 8))
+    b = mi.uniform_f64(rng, (8, 4, 4))
+    g = mi.uniform_f64(rng, (4, 4, 4, 4))
+    ta = gpu(a).requires_grad_(True)
+    tb = gpu(b).requires_grad_(True)
+    gg = gpu(g)
+    say("grad FD through MoaInner.apply")
+    loss = torch.sum(moa.MoaInner.apply(ta, tb) * gg)
+    da, db = torch.autograd.grad(loss, (ta, tb))
+    da, db = host(da), host(db)
+    h = 2.0 ** -8
+
+    def L(x, y):
+        with torch.no_grad():
+            return float(torch.sum(moa.MoaInner.apply(gpu(x), gpu(y)) * gg).item())
+
+    fa = np.zeros_like(a)
+    for idx in np.ndindex(a.shape):
+        ap, am = a.copy(), a.copy()
+        ap[idx] += h
+        am[idx] -= h
+        fa[idx] = (L(ap, b) - L(am, b)) / (2 * h)
+    fb = np.zeros_like(b)
+    for idx in np.ndindex(b.shape):
+        bp, bm = b.copy(), b.copy()
+        bp[idx] += h
+        bm[idx] -= h
+        fb[idx] = (L(a, bp) - L(a, bm)) / (2 * h)
+    assert np.max(np.abs(fa - da)) <= 1e-12
+    assert np.max(np.abs(fb - db)) <= 1e-12
+    # Only the input that needs a gradient gets one.
+    tc = gpu(b)
+    (only_a,) = torch.autograd.grad(torch.sum(moa.MoaInner.apply(ta, tc) * gg), (ta,))
+    eq(host(only_a), da)
+
+
+# ---------------------------------------------------------------------------
+# NaN and signed zero: FP max/min are the IEEE 754-2019 maximum/minimum and
+# FP folds equal the left fold from the first term, on every fold path,
+# compared bit for bit.
+
+SPECIAL = np.array([-0.0, 0.0, -0.0, 0.0, 1.0, -1.0, 2.0, -2.0, np.inf, np.nan], dtype=np.float64)
+
+
+def _special(rng, shape, dt, nan=True):
+    pool = SPECIAL if nan else SPECIAL[:-1]
+    return np.ascontiguousarray(rng.choice(pool, size=shape).astype(dt))
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_nan_and_signed_zero_sequential_folds(dt):
+    rng = np.random.default_rng(170)
+    for sa, sb in [((37, 19), (19, 53)), ((6, 1), (1, 9)), ((133, 21), (21, 70))]:
+        a, b = _special(rng, sa, dt), _special(rng, sb, dt)
+        ga, gb = gpu(a), gpu(b)
+        for op1 in FOLD_F:
+            for op2 in ELEM_F:
+                say("special values, simt", np.dtype(dt).name, sa, sb, op1, op2)
+                got = host(G.inner_ex(ga, gb, op1, op2, flags=moa.FLAG_SEQUENTIAL_FOLD))
+                eq(got, oracle.inner(a, b, op1, op2, mode="native"))
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_nan_and_signed_zero_few_rows_and_columns(dt):
+    # Few rows (the row-form stream) for every fold, few columns (the
+    # cross-lane reduction) for max and min: both bit for bit.
+    rng = np.random.default_rng(171)
+    a, b = _special(rng, (3, 64), dt), _special(rng, (64, 4100), dt)
+    ga, gb = gpu(a), gpu(b)
+    for op1 in FOLD_F:
+        for op2 in ("add", "mul", "max", "min"):
+            say("special values, few rows", np.dtype(dt).name, op1, op2)
+            eq(host(G.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
+    # Mostly zeros and ones with a few NaNs: max/min results often tie at +-0.
+    a = np.ascontiguousarray(rng.choice(SPECIAL[:5], size=(70, 600)).astype(dt))
+    b = np.ascontiguousarray(rng.choice(SPECIAL[:5], size=(600, 5)).astype(dt))
+    a[3, 7] = np.nan
+    for op1 in ("max", "min"):
+        for op2 in ("add", "mul", "max", "min", "sub"):
+            say("special values, few columns", np.dtype(dt).name, op1, op2)
+            eq(host(G.inner(gpu(a), gpu(b), op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_nan_and_signed_zero_outer(dt):
+    rng = np.random.default_rng(172)
+    a, b = _special(rng, (17, 3), dt), _special(rng, (2, 129), dt)
+    for op in ELEM_F:
+        eq(host(G.outer(gpu(a), gpu(b), op)), oracle.outer(a, b, op))
+
+
+# ---------------------------------------------------------------------------
+# Few-row stream instances that the cache-resident path never reaches: B
+# larger than 64 MiB or at least 1024 column blocks keep every row in one
+# thread (row groups of 2, 4 or 8; rows past M repeat row M - 1 unstored),
+# one or four 16-byte runs per thread, ragged and unaligned column counts.
+
+SKINNY_BIG = [
+    (np.float64, 5, 16, 600_001, "FP64, R = 1, row group 8, ragged N"),
+    (np.float64, 3, 16, 600_000, "FP64, R = 1, row group 4, vector loads"),
+    (np.float64, 7, 8, 1_048_578, "FP64, R = 4, row group 8, vector loads"),
+    (np.float64, 3, 8, 1_048_579, "FP64, R = 4, row group 4, odd N"),
+    (np.int32, 8, 8, 1_100_003, "int32, R = 1, row group 8, odd N"),
+    (np.int32, 3, 8, 2_100_004, "int32, R = 4, row group 4, vector loads"),
+    (np.int32, 5, 8, 2_100_001, "int32, R = 4, row group 8, odd N"),
+]
+
+
+@pytest.mark.parametrize("case", SKINNY_BIG, ids=[c[4] for c in SKINNY_BIG])
+def test_few_rows_all_rows_per_thread(case):
+    dt, M, K, N, what = case
+    rng = np.random.default_rng(173)
+    a, b = rand(rng, (M, K), dt), rand(rng, (K, N), dt)
+    ga, gb = gpu(a), gpu(b)
+    pairs = ([("add", "mul"), ("max", "add"), ("min", "sub"), ("xor", "and")] if dt == np.int32 else
+             [("add", "mul"), ("max", "add"), ("min", "sub"), ("mul", "div")])
+    for op1, op2 in pairs:
+        say("few rows", what, op1, op2)
+        eq(host(G.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))

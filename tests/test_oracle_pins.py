@@ -34,12 +34,15 @@ def _rand(rng, shape, dtype):
 
 
 def _equal(x, y):
+    """Equal bit for bit (so +0 and -0 differ); any NaN matches any NaN."""
     x = np.asarray(x)
     y = np.asarray(y)
-    assert x.shape == y.shape
+    assert x.shape == y.shape and x.dtype == y.dtype, (x.shape, y.shape, x.dtype, y.dtype)
     if x.dtype.kind == "f":
+        u = np.dtype("u%d" % x.dtype.itemsize)
         both_nan = np.isnan(x) & np.isnan(y)
-        assert np.all((x == y) | both_nan), np.max(np.abs(x - y))
+        same = x.view(u) == y.view(u)
+        assert np.all(same | both_nan), (x[~(same | both_nan)][:4], y[~(same | both_nan)][:4])
     else:
         assert np.array_equal(x, y)
 
@@ -535,3 +538,107 @@ def test_componentwise_error_meets_recursive_summation_bound():
     # to near zero and the same error exceeds the bound.
     bad = oracle.componentwise_error(got, ref, np.abs(oracle.inner(a.astype(np.float64), b.astype(np.float64))))
     assert bad > err
+
+
+def test_normwise_error_hand_values():
+    # ||x - ref||_F / ||ref||_F: 3-4-5 triangles make every value exact.
+    assert oracle.normwise_error([3.0, 4.0], [3.0, 4.0]) == 0.0
+    assert oracle.normwise_error([0.0, 0.0], [3.0, 4.0]) == 1.0
+    # The denominator is the reference's norm (5), not the result's (10).
+    assert oracle.normwise_error([6.0, 8.0], [3.0, 4.0]) == 1.0
+    # Frobenius over a matrix: ||ref||_F = 5, ||x - ref||_F = 3.
+    ref = [[1.0, 2.0], [2.0, 4.0]]
+    assert oracle.normwise_error([[1.0, 2.0], [2.0, 7.0]], ref) == 0.6
+    assert oracle.normwise_error([[2.0, 0.0], [0.0, 4.0]], ref) == 0.6
+    # A zero reference: the absolute norm of the difference.
+    assert oracle.normwise_error([3.0, -4.0], [0.0, 0.0]) == 5.0
+
+
+# --------------------------------------------------------------------------
+# FP max / min: the IEEE 754-2019 maximum and minimum (NaN if either operand
+# is NaN, -0 below +0), the reading taken where the paper is silent on NaN and
+# signed zero. These rules make both operations associative and commutative.
+
+NZ, PZ, NAN = -0.0, 0.0, float("nan")
+
+
+def _bits(x):
+    return np.asarray(x, dtype=np.float64).view(np.uint64)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_max_min_nan_and_signed_zero_hand_values(dt):
+    a = np.array([NZ, PZ, NAN, 1.0], dtype=dt)
+    b = np.array([PZ, NZ, 2.0], dtype=dt)
+    # max: -0 vs +0 gives +0 in either order; NaN wins; otherwise the larger.
+    want_max = np.array([[PZ, NZ, 2.0], [PZ, PZ, 2.0], [NAN, NAN, NAN], [1.0, 1.0, 2.0]], dtype=dt)
+    want_min = np.array([[NZ, NZ, NZ], [PZ, NZ, PZ], [NAN, NAN, NAN], [PZ, NZ, 1.0]], dtype=dt)
+    _equal(oracle.outer(a, b, "max"), want_max)
+    _equal(oracle.outer(a, b, "min"), want_min)
+    _equal(brute.outer(a, b, "max"), want_max)
+    _equal(brute.outer(a, b, "min"), want_min)
+    # Fold over [NaN, 5] in either order: NaN (an order-dependent rule such as
+    # "a < b ? b : a" gives 5 one way round).
+    for row in ([NAN, 5.0], [5.0, NAN]):
+        x = np.array([row], dtype=dt)
+        z = np.zeros((2, 1), dtype=dt)
+        assert np.isnan(oracle.inner(x, z, "max", "add", mode="native")).all()
+        assert np.isnan(oracle.inner(x, z, "min", "add", mode="native")).all()
+    # Terms (+0, -0) and (-0, +0): max +0, min -0.
+    for row in ([1.0, -1.0], [-1.0, 1.0]):
+        x = np.array([row], dtype=dt)
+        z = np.zeros((2, 1), dtype=dt)
+        _equal(oracle.inner(x, z, "max", "mul", mode="native"), np.array([[PZ]], dtype=dt))
+        _equal(oracle.inner(x, z, "min", "mul", mode="native"), np.array([[NZ]], dtype=dt))
+    # A sum of -0 terms is -0 (the left fold from the first term), a sum of
+    # +0 and -0 terms +0.
+    x = np.array([[-1.0, -2.0, -3.0]], dtype=dt)
+    _equal(oracle.inner(x, np.zeros((3, 1), dtype=dt), "add", "mul", mode="native"), np.array([[NZ]], dtype=dt))
+    x = np.array([[-1.0, 2.0, -3.0]], dtype=dt)
+    _equal(oracle.inner(x, np.zeros((3, 1), dtype=dt), "add", "mul", mode="native"), np.array([[PZ]], dtype=dt))
+
+
+def test_max_min_fold_independent_of_order():
+    # Any permutation of the terms folds to the same bits (NaN-ness for NaN).
+    rng = np.random.default_rng(61)
+    pool = np.array([NZ, PZ, NZ, PZ, 1.5, -1.5, np.inf, -np.inf, NAN, 3.0], dtype=np.float64)
+    for trial in range(200):
+        terms = rng.choice(pool, size=rng.integers(1, 7))
+        if trial % 3:
+            terms = terms[~np.isnan(terms)] if (~np.isnan(terms)).any() else terms
+        for op in ("max", "min"):
+            a = terms[None, :]
+            b = np.zeros((len(terms), 1))
+            want = oracle.inner(a, b, op, "add")
+            for _ in range(4):
+                p = rng.permutation(len(terms))
+                got = oracle.inner(terms[p][None, :], b, op, "add")
+                if np.isnan(want).all():
+                    assert np.isnan(got).all()
+                else:
+                    assert _bits(got) == _bits(want), (op, terms, p)
+
+
+def test_max_min_with_nan_and_zeros_match_brute_force():
+    rng = np.random.default_rng(62)
+    pool = np.array([NZ, PZ, 1.0, -1.0, 2.0, NAN, np.inf], dtype=np.float64)
+    for dt in (np.float64, np.float32):
+        a = rng.choice(pool, size=(3, 4, 5)).astype(dt)
+        b = rng.choice(pool, size=(5, 6)).astype(dt)
+        for op1 in ("max", "min", "add", "mul"):
+            for op2 in ("add", "mul", "max", "min"):
+                _equal(oracle.inner(a, b, op1, op2, mode="native"), brute.inner(a, b, op1, op2))
+
+
+def test_split_s5_beta9_meets_tolerance_on_more_seeds():
+    # The chosen BF16 parameters (9-bit digits, 5 slices) on six further
+    # seeds of the workload distribution (entries u 2^k, k in [-8, 8]) at
+    # K = 8192, each against Dot2; all must stay within 1e-12.
+    errs = []
+    for salt in (11, 12, 13, 14, 15, 16):
+        rng = mi.rng_for(mi.SPLIT_PRECISION, salt=salt)
+        a = mi.scaled_f64(rng, (8, 8192))
+        b = mi.scaled_f64(rng, (8192, 24))
+        ref = oracle.inner_dot2(a, b)
+        errs.append(oracle.normwise_error(oracle.split_inner(a, b, nslices=5, beta=9), ref))
+    assert max(errs) <= 1e-12, errs
