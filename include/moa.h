@@ -188,6 +188,25 @@ moa_status moa_inner_split_multiply(moa_shape sa, moa_shape sb, double *D, int32
                                     size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * moa_inner_split without a workspace and without any allocation, for callers
+ * that cannot allocate device memory (code being captured into a HIP graph,
+ * tight serving loops, harnesses that forbid hipMalloc). The scratch lives in
+ * a static device array of MOA_SPLIT_STATIC_BYTES bytes that each GPU the
+ * library runs on holds until the process ends. Same arguments, results and
+ * errors as moa_inner_split minus ws / ws_bytes; a problem whose workspace
+ * (moa_inner_split_workspace) exceeds MOA_SPLIT_STATIC_BYTES is refused with
+ * MOA_ERR_WORKSPACE before any launch (at S = 5 BF16 slices that admits
+ * square products up to about 2500^3). Every call on one GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other streams, other host
+ * threads) race; calls in one stream are ordered and safe. The array keeps
+ * the last call's contents; everything a call reads from it, the call has
+ * written first (the column maxima are cleared by a kernel).
+ */
+#define MOA_SPLIT_STATIC_BYTES ((size_t)128 << 20)
+moa_status moa_inner_split_static(moa_shape sa, const double *A, moa_shape sb, const double *B, double *D,
+                                  int32_t fmt, int32_t nslices, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Backward of the (+,*) inner product D = A . B (FP32 or FP64).
  * G: upstream gradient dL/dD with the result shape. Writes
  *   dA = G (+,*) B_rot   (B_rot: B with its first axis moved last)  shape sa

@@ -79,6 +79,7 @@ def lib():
     L.moa_inner_split.argtypes = [S, vp, S, vp, vp, i32, i32, vp, sz, vp]
     L.moa_inner_split_prepare.argtypes = [S, vp, S, vp, i32, i32, vp, sz, vp]
     L.moa_inner_split_multiply.argtypes = [S, S, vp, i32, i32, vp, sz, vp]
+    L.moa_inner_split_static.argtypes = [S, vp, S, vp, vp, i32, i32, vp]
     L.moa_inner_grad.argtypes = [S, vp, S, vp, vp, vp, vp, i32, vp]
     L.moa_batch_build.argtypes = [i32, ctypes.POINTER(S), ctypes.POINTER(vp), ctypes.POINTER(S), ctypes.POINTER(vp),
                                   ctypes.POINTER(vp), i32, vp, ctypes.POINTER(vp)]
@@ -91,7 +92,7 @@ def lib():
     L.moa_tile_table_set.argtypes = [ctypes.c_char_p]
     for name in ("moa_inner_shape", "moa_outer_shape", "moa_inner", "moa_inner_ex", "moa_outer", "moa_inner_split",
                  "moa_inner_axes_shape", "moa_inner_axes",
-                 "moa_inner_split_prepare", "moa_inner_split_multiply", "moa_inner_grad", "moa_batch_build", "moa_batch_run", "moa_batch_info", "moa_batch_autotune",
+                 "moa_inner_split_prepare", "moa_inner_split_multiply", "moa_inner_split_static", "moa_inner_grad", "moa_batch_build", "moa_batch_run", "moa_batch_info", "moa_batch_autotune",
                  "moa_tile_table_get", "moa_tile_table_set"):
         getattr(L, name).restype = i32
     _lib = L
@@ -282,6 +283,25 @@ def inner_split(a: torch.Tensor, b: torch.Tensor, fmt: str = "bf16", nslices: in
         _check_workspace(workspace, dev)
     _check(lib().moa_inner_split(_shape(a.shape), _ptr(a), _shape(b.shape), _ptr(b), _ptr(out), SPLIT_FORMATS[fmt],
                                  nslices, ctypes.c_void_p(workspace.data_ptr()), _nbytes(workspace), _stream(dev)))
+    return out
+
+
+def inner_split_static(a: torch.Tensor, b: torch.Tensor, fmt: str = "bf16", nslices: int = 5,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+    """inner_split with the library's static scratch instead of a workspace
+    (moa_inner_split_static: no device allocation inside the library)."""
+    if a.dtype != torch.float64 or b.dtype != torch.float64:
+        raise TypeError("inner_split_static takes float64 operands")
+    dev = _dev_operands(a, b)
+    a = a.contiguous()
+    b = b.contiguous()
+    rs = inner_shape(a.shape, b.shape)
+    if out is None:
+        out = torch.empty(rs, dtype=torch.float64, device=dev)
+    else:
+        _check_out(out, rs, torch.float64, dev)
+    _check(lib().moa_inner_split_static(_shape(a.shape), _ptr(a), _shape(b.shape), _ptr(b), _ptr(out),
+                                        SPLIT_FORMATS[fmt], nslices, _stream(dev)))
     return out
 
 
