@@ -12,7 +12,9 @@ Printed (one JSON line): Gop/s of the split path (2*M*N*K algorithmic ops per
 step), the plain FP64 matrix-core kernel on the same inputs for comparison,
 the roofline of the dominant kernel (slice-pair product: BF16 MFMA flops per
 launch / its average HIP-event duration, against 2516.6 TFLOP/s dense BF16),
-and the CPU oracle timed on a bounded sample of rows.
+and the oracle leg: the CPU oracle timed on a bounded sample of rows, and the
+normwise / max-norm / componentwise error of the BF16, INT8 and plain FP64
+results against the oracle's compensated product on 16 sampled rows.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
@@ -96,6 +98,20 @@ def cpu_baseline(a, b, target_s=12.0):
     return {"value": ops / dt / 1e9, "unit": "Gop/s", "cores": cores, "kind": "oracle",
             "sample": "%d of 8192 result rows (%.3g ops, %.1f s), plain FP64 fold of the psi definition" %
                       (nrows, ops, dt)}
+
+
+def oracle_errors(a, b, results, rows):
+    """Error of each GPU result (host copies of the sampled rows) against the
+    oracle's compensated FP64 product (Dot2) on the same rows: normwise (the
+    gate), max-norm and componentwise (|A||B| scale)."""
+    import oracle
+    ref = oracle.inner_dot2(a, b, rows=rows)
+    scale = oracle.abs_product(a, b, rows=rows)
+    out = {}
+    for name, got in results.items():
+        out[name] = {"normwise": oracle.normwise_error(got, ref), "maxnorm": oracle.maxnorm_error(got, ref),
+                     "componentwise": oracle.componentwise_error(got, ref, scale)}
+    return out
 
 
 def cpu_oracle_small_single_thread():
@@ -456,6 +472,12 @@ def main():
     mult8 = sum(e[1].elapsed_time(e[2]) for e in evs8) / args.steps
     prep8 = sum(e[0].elapsed_time(e[1]) for e in evs8) / args.steps
     diff8 = float(torch.linalg.norm(d8[rows] - dp[rows]) / torch.linalg.norm(dp[rows]))
+    # Host copies of seeded sample rows of the three results, for the oracle
+    # leg's error report (after every timed region).
+    err_rows = np.sort(np.random.default_rng(4321).choice(n, 16, replace=False))
+    er = torch.from_numpy(err_rows).to(dev)
+    sampled = {"split_bf16": d[er].cpu().numpy(), "split_int8": d8[er].cpu().numpy(),
+               "plain_fp64": dp[er].cpu().numpy()}
     int8_ops = S8 * (S8 + 1) // 2 * ops / (mult8 * 1e-3) / 1e12
     split_int8 = {"value": round(ops * args.steps / el8 / 1e9, 3), "unit": "Gop/s",
                   "ms_per_step": round(el8 * 1e3 / args.steps, 4),
@@ -493,6 +515,16 @@ def main():
                      "traffic": traffic_from_profiles(launch_flops)},
     }
     if not args.no_cpu_baseline:
+        # The oracle leg: the oracle timed on the host cores, and the error of
+        # every result against it on the sampled rows.
+        log("bench: error against the oracle on %d sampled rows" % len(err_rows))
+        errs = oracle_errors(a_h, b_h, sampled, err_rows)
+        bound = 1e-12
+        ok = all(errs[k]["normwise"] <= bound for k in ("split_bf16", "split_int8"))
+        result["error_vs_oracle"] = dict(errs, reference="oracle Dot2 (compensated FP64)",
+                                         rows=len(err_rows), bound_normwise=bound, within_bound=ok)
+        if not ok:
+            log("bench: WARNING: a split result exceeds the %.0e normwise bound: %s" % (bound, errs))
         log("bench: CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(a_h, b_h)
         result["cpu_oracle_512_one_thread"] = cpu_oracle_small_single_thread()

@@ -68,11 +68,19 @@ typedef struct moa_shape {
   const int64_t *dims;  /* host array of `rank` extents (may be NULL when rank == 0) */
 } moa_shape;
 
-typedef enum moa_dtype { MOA_F64 = 0, MOA_F32 = 1, MOA_I32 = 2 } moa_dtype;
+/* The *_RANGE_ enumerators are not values to pass: they make every int32
+ * value a valid value of the enum type, so a wrong code a caller passes is
+ * rejected by the validation (MOA_ERR_DTYPE / MOA_ERR_OP) rather than being
+ * undefined behaviour in the library. */
+typedef enum moa_dtype {
+  MOA_F64 = 0, MOA_F32 = 1, MOA_I32 = 2,
+  MOA_DTYPE_RANGE_MIN_ = -2147483647 - 1, MOA_DTYPE_RANGE_MAX_ = 2147483647
+} moa_dtype;
 
 typedef enum moa_op {
   MOA_ADD = 0, MOA_SUB = 1, MOA_MUL = 2, MOA_DIV = 3, MOA_MAX = 4,
-  MOA_MIN = 5, MOA_AND = 6, MOA_OR = 7, MOA_XOR = 8
+  MOA_MIN = 5, MOA_AND = 6, MOA_OR = 7, MOA_XOR = 8,
+  MOA_OP_RANGE_MIN_ = -2147483647 - 1, MOA_OP_RANGE_MAX_ = 2147483647
 } moa_op;
 
 typedef enum moa_status {
@@ -86,7 +94,8 @@ typedef enum moa_status {
   MOA_ERR_ALIAS = 7,      /* output overlaps an input */
   MOA_ERR_WORKSPACE = 8,  /* workspace missing or too small */
   MOA_ERR_HIP = 9,        /* a HIP runtime call failed */
-  MOA_ERR_ARG = 10        /* other invalid argument (format, slice count, ...) */
+  MOA_ERR_ARG = 10,       /* other invalid argument (format, slice count, ...) */
+  MOA_STATUS_RANGE_MIN_ = -2147483647 - 1, MOA_STATUS_RANGE_MAX_ = 2147483647
 } moa_status;
 
 /* Status name, static string. */

@@ -70,6 +70,41 @@ def build(verbose: bool = False, jobs: int | None = None, force: bool = True) ->
     return LIB
 
 
+# Units with host logic (argument validation, shape algebra, the tile-table
+# parser, batch building, the static scratch lookup).
+HOST_UNITS = ("moa_abi.hip", "k_batch.hip", "split_static.hip")
+
+
+def build_host_sanitized(out: str, verbose: bool = False) -> str:
+    """A copy of the library whose host code is built with AddressSanitizer
+    and UndefinedBehaviorSanitizer (device code as usual), for CPU tests of
+    the host logic. The other units' objects come from the regular build;
+    the process that loads it must preload clang's ASan runtime."""
+    objs = []
+    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+        name = os.path.basename(src)
+        obj = os.path.join(BUILD, name.replace(".hip", ".o"))
+        if name in HOST_UNITS:
+            obj = out + "." + name.replace(".hip", ".o")
+            cmd = [HIPCC] + CFLAGS + ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                                      "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host",
+                                      "-fno-omit-frame-pointer", "-c", src, "-o", obj]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr))
+        elif not os.path.exists(obj):
+            raise FileNotFoundError("%s is not built: run the regular build first" % obj)
+        objs.append(obj)
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", "-o", out] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n%s" % r.stderr)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv, force="--changed" not in sys.argv)
     print("built", LIB)

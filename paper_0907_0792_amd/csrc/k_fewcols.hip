@@ -253,6 +253,7 @@ hipError_t launch_fewcols_inner(moa_dtype dt, moa_op op1, moa_op op2, const void
       return dispatch_int<int32_t>(op1, op2, (const int32_t *)A, (const int32_t *)B, (int32_t *)D, M, K, N, s);
     case MOA_F32: return dispatch_fp<float>(op1, op2, (const float *)A, (const float *)B, (float *)D, M, K, N, s);
     case MOA_F64: return dispatch_fp<double>(op1, op2, (const double *)A, (const double *)B, (double *)D, M, K, N, s);
+    default: break;
   }
   return hipErrorInvalidValue;
 }

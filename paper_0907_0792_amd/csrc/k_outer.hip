@@ -104,6 +104,7 @@ hipError_t launch_outer(moa_dtype dt, moa_op op, const void *A, const void *B, v
     case MOA_F64: return dispatch<double>(op, (const double *)A, (const double *)B, (double *)C, NA, NB, s);
     case MOA_F32: return dispatch<float>(op, (const float *)A, (const float *)B, (float *)C, NA, NB, s);
     case MOA_I32: return dispatch<int32_t>(op, (const int32_t *)A, (const int32_t *)B, (int32_t *)C, NA, NB, s);
+    default: break;
   }
   return hipErrorInvalidValue;
 }

@@ -79,6 +79,7 @@ hipError_t launch_simt_inner(moa_dtype dt, moa_op op1, moa_op op2, const void *A
       return dispatch_op1<float>(op1, op2, (const float *)A, (const float *)B, (float *)D, M, K, N, tile, Qa, Qb, s);
     case MOA_I32:
       return dispatch_op1<int32_t>(op1, op2, (const int32_t *)A, (const int32_t *)B, (int32_t *)D, M, K, N, tile, Qa, Qb, s);
+    default: break;
   }
   return hipErrorInvalidValue;
 }

@@ -42,6 +42,7 @@ size_t elem_size(moa_dtype dt) {
     case MOA_F64: return 8;
     case MOA_F32: return 4;
     case MOA_I32: return 4;
+    default: break;
   }
   return 0;
 }
@@ -64,6 +65,7 @@ bool is_elem_op(moa_op op, moa_dtype dt) {
     case MOA_AND:
     case MOA_OR:
     case MOA_XOR: return dt == MOA_I32;
+    default: break;
   }
   return false;
 }
@@ -219,6 +221,7 @@ const char *moa_status_str(moa_status s) {
     case MOA_ERR_WORKSPACE: return "MOA_ERR_WORKSPACE";
     case MOA_ERR_HIP: return "MOA_ERR_HIP";
     case MOA_ERR_ARG: return "MOA_ERR_ARG";
+    default: break;
   }
   return "MOA_ERR_UNKNOWN";
 }
