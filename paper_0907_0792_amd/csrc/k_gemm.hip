@@ -16,6 +16,8 @@
 // is how the backward pass contracts over permuted axes without a transposed
 // copy; the GEN variants read the strided (P, K, Q) views of a contraction
 // over any axis pair.
+#include <utility>
+
 #include "common.hpp"
 #include "gemm_tile.hpp"
 #include "internal.hpp"
@@ -43,6 +45,153 @@ __global__ __launch_bounds__(256, (gemm_min_blocks<T, WBM, VEC, I>())) void k_ge
       A, B, D, (I)M, (I)K, (I)N, (I)(tm * 32 * WBM), (I)(tn * 32 * WBN), (I)Qa, (I)Qb);
 }
 
+// Small grids (fewer 32 x 32 tiles than the GPU has SIMDs) with a long
+// contraction: one 32 x 32 tile per workgroup of KG groups of 4 waves. Group
+// g takes the k panels g, g + KG, g + 2 KG, ..., keeping DEPTH panels in
+// flight in registers, so each wave waits out about nk / (KG DEPTH) load
+// round trips instead of nk, and each SIMD holds KG waves instead of one.
+// Panels are staged in two LDS buffers (one barrier per panel). The groups'
+// partial tiles are summed in LDS in group order (deterministic). FP64 512^3:
+// 15-17 us with the one-group kernel.
+template <typename T, int KG, int BK, int DEPTH, bool VEC>
+__global__ __launch_bounds__(256 * KG, 1) void k_gemm_splitk(const T *__restrict__ A, const T *__restrict__ B,
+                                                             T *__restrict__ D, int64_t M, int64_t K, int64_t N,
+                                                             int64_t tiles_m, int64_t tiles_n) {
+  using MF = Mfma16<T>;
+  using acc_t = typename MF::acc_t;
+  constexpr int BM = 32, BN = 32, PAD = 2;
+  constexpr int V = VEC ? 16 / (int)sizeof(T) : 1;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;  // elements per thread per panel
+  typedef __attribute__((__vector_size__(V * sizeof(T)))) T vec_t;
+  // A is staged row-major (its rows are what the lanes load, 16-byte runs
+  // along k), padded by 16 bytes so the 16 rows of a fragment read start in
+  // different banks; B k-major.
+  constexpr int PA = 16 / (int)sizeof(T);
+  __shared__ T As[2][KG][BM][BK + PA];
+  __shared__ T Bs[2][KG][BK][BN + PAD];
+  static_assert(sizeof(As) >= sizeof(T) * 4 * 256 * (KG - 1), "reduction space");
+
+  int64_t tm, tn;
+  grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x % 256, lane = tid % kWave;
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x / 256);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int wm = wave / 2, wn = wave % 2;
+
+  // Loads are unconditional (an element past an edge reads element 0 and is
+  // zeroed when stored), so they issue as straight-line code and the wait
+  // before a store covers only that panel's loads, not the later ones.
+  // (Whether an element is inside is recomputed at the store: keeping the
+  // flags would cost registers.)
+  vec_t ra[DEPTH][EA / V], rb[DEPTH][EB / V];
+  auto a_in = [&](int e, int64_t k0) {
+    const int f = tid + 256 * e;
+    return m0 + f / (BK / V) < M && k0 + (f % (BK / V)) * V < K;
+  };
+  auto b_in = [&](int e, int64_t k0) {
+    const int f = tid + 256 * e;
+    return n0 + (f % (BN / V)) * V < N && k0 + f / (BN / V) < K;
+  };
+  auto load = [&](auto bufc, int64_t k0) {
+    constexpr int buf = decltype(bufc)::value;
+#pragma unroll
+    for (int e = 0; e < EA / V; ++e) {
+      const int f = tid + 256 * e;
+      const int64_t gm = m0 + f / (BK / V), gk = k0 + (f % (BK / V)) * V;
+      ra[buf][e] = *(const vec_t *)(A + (a_in(e, k0) ? gm * K + gk : 0));
+    }
+#pragma unroll
+    for (int e = 0; e < EB / V; ++e) {
+      const int f = tid + 256 * e;
+      const int64_t gk = k0 + f / (BN / V), gn = n0 + (f % (BN / V)) * V;
+      rb[buf][e] = *(const vec_t *)(B + (b_in(e, k0) ? gk * N + gn : 0));
+    }
+  };
+  auto store = [&](auto bufc, int lb, int64_t k0) {
+    constexpr int buf = decltype(bufc)::value;
+#pragma unroll
+    for (int e = 0; e < EA / V; ++e) {
+      const int f = tid + 256 * e;
+      const bool in = a_in(e, k0);
+#pragma unroll
+      for (int u = 0; u < V; ++u) As[lb][g][f / (BK / V)][(f % (BK / V)) * V + u] = in ? ra[buf][e][u] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < EB / V; ++e) {
+      const int f = tid + 256 * e;
+      const bool in = b_in(e, k0);
+#pragma unroll
+      for (int u = 0; u < V; ++u) Bs[lb][g][f / (BN / V)][(f % (BN / V)) * V + u] = in ? rb[buf][e][u] : T(0);
+    }
+  };
+
+  // Two accumulators (even and odd k steps) break the MFMA dependency chain.
+  acc_t acc[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[h][v] = T(0);
+
+  const int64_t nk = (K + BK - 1) / BK;
+  const int64_t live = (nk + KG - 1) / KG;  // rounds with a panel for some group
+  // Every group runs the same number of rounds, a multiple of DEPTH, so the
+  // loop body has no branch around a load; rounds past `live` only load.
+  const int64_t rounds = (live + DEPTH - 1) / DEPTH * DEPTH;
+  // Round r multiplies panel r from LDS buffer r % 2 while the stores of
+  // panel r + 1 (register set (r + 1) % DEPTH) fill the other buffer, which
+  // every wave finished reading in round r - 1, and that register set is
+  // refilled with panel r + 1 + DEPTH; one barrier ends the round. The MFMAs
+  // of a round thus overlap the next panel's LDS stores.
+  auto round = [&](int64_t r, auto bufc) {
+    constexpr int nbuf = (decltype(bufc)::value + 1) % DEPTH;
+    const int lb = (int)(r & 1);
+    if (r < live) {
+#pragma unroll
+      for (int k4 = 0; k4 < BK; k4 += 4) {
+        const T a = As[lb][g][wm * 16 + lane % 16][k4 + lane / 16];
+        const T b = Bs[lb][g][k4 + lane / 16][wn * 16 + lane % 16];
+        acc[(k4 / 4) & 1] = MF::run(a, b, acc[(k4 / 4) & 1]);
+      }
+    }
+    store(std::integral_constant<int, nbuf>{}, lb ^ 1, ((r + 1) * KG + g) * BK);
+    load(std::integral_constant<int, nbuf>{}, ((r + 1 + DEPTH) * KG + g) * BK);
+    __syncthreads();
+  };
+  [&]<int... J>(std::integer_sequence<int, J...>) {
+    (load(std::integral_constant<int, J>{}, ((int64_t)J * KG + g) * BK), ...);
+  }(std::make_integer_sequence<int, DEPTH>{});
+  store(std::integral_constant<int, 0>{}, 0, (int64_t)g * BK);
+  load(std::integral_constant<int, 0>{}, ((int64_t)DEPTH * KG + g) * BK);
+  __syncthreads();
+  for (int64_t r = 0; r < rounds; r += DEPTH) {
+    [&]<int... J>(std::integer_sequence<int, J...>) {
+      (round(r + J, std::integral_constant<int, J>{}), ...);
+    }(std::make_integer_sequence<int, DEPTH>{});
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[0][v] += acc[1][v];
+  // Groups 1..KG-1 hand their partial tiles to group 0 through LDS.
+  __syncthreads();
+  T *red = &As[0][0][0][0];
+  if (g > 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[((g - 1) * 4 + v) * 256 + tid] = acc[0][v];
+  }
+  __syncthreads();
+  if (g == 0) {
+#pragma unroll
+    for (int q = 1; q < KG; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[0][v] += red[((q - 1) * 4 + v) * 256 + tid];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gm = m0 + wm * 16 + MF::row(lane, v), gn = n0 + wn * 16 + lane % 16;
+      if (gm < M && gn < N) D[gm * N + gn] = acc[0][v];
+    }
+  }
+}
+
 // Every offset of a tile of M x K . K x N (extents padded by a 128 tile) fits
 // in 31 bits.
 static bool fits_int32(int64_t M, int64_t K, int64_t N) {
@@ -61,10 +210,21 @@ static int auto_tile(int64_t M, int64_t N) {
 template <typename T, bool TA, bool TB, bool GEN, bool VEC>
 static hipError_t launch_t(const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, int tile, int64_t Qa,
                            int64_t Qb, hipStream_t s) {
+  const bool automatic = tile == 0;
   if (tile == 0) tile = auto_tile(M, N);
   if (tile == 3) {
     const int64_t tmn = (M + 31) / 32, tnn = (N + 31) / 32;
     if (tmn * tnn > 0x7fffffff) return hipErrorInvalidConfiguration;
+    if constexpr (!TA && !TB && !GEN) {
+      // Fewer 32 x 32 tiles than SIMDs and a contraction of at least 256:
+      // split it over four wave groups per tile.
+      if (automatic && tmn * tnn < 1024 && K >= 256) {
+        // 32-wide panels, two in flight per thread beyond the one in LDS.
+        hipLaunchKernelGGL((k_gemm_splitk<T, 4, 32, 2, VEC>), dim3((unsigned)(tmn * tnn)), dim3(1024), 0, s, A, B, D,
+                           M, K, N, tmn, tnn);
+        return hipGetLastError();
+      }
+    }
     hipLaunchKernelGGL((k_gemm<T, TA, TB, 1, 1, GEN, VEC>), dim3((unsigned)(tmn * tnn)), dim3(256), 0, s, A, B, D, M, K,
                        N, tmn, tnn, Qa, Qb);
   } else if (tile == 1) {

@@ -411,12 +411,15 @@ def test_mfma_f32_large_tiles_transposed_operands():
 
 def test_mfma_f64_exact_integers():
     # Integer entries with |x| <= 8 and K <= 8192: every partial sum is exact,
-    # so any summation order gives the exact product.
+    # so any summation order gives the exact product. Small grids with long
+    # contractions (the first two) split k over wave groups.
     rng = np.random.default_rng(104)
-    a = mi.small_int_f64(rng, (200, 1000), 8)
-    b = mi.small_int_f64(rng, (1000, 130), 8)
-    say("mfma exact ints")
-    eq(host(G.inner(gpu(a), gpu(b))), (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
+    for sa, sb in [((200, 1000), (1000, 130)), ((97, 333), (333, 61)), ((512, 512), (512, 512)),
+                   ((1100, 300), (300, 700))]:
+        a = mi.small_int_f64(rng, sa, 8)
+        b = mi.small_int_f64(rng, sb, 8)
+        say("mfma exact ints", sa, sb)
+        eq(host(G.inner(gpu(a), gpu(b))), (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
 
 
 # ---------------------------------------------------------------------------
@@ -1015,6 +1018,8 @@ FP32_GEMM_VARIANTS = [
     ((7, 45, 33), 1, (20, 45, 13), 1, "strided views (GEN), scalar"),
     ((5, 36, 8), 1, (12, 36, 20), 1, "strided views (GEN), vector panels"),
     ((3, 2, 70), 2, (70, 5, 9), 0, "rank 3 . rank 3"),
+    ((200, 1000), 1, (1000, 132), 0, "32x32 tiles, k split over 4 wave groups, vector panels"),
+    ((97, 333), 1, (333, 61), 0, "32x32 tiles, k split over 4 wave groups, scalar panels"),
 ]
 
 
