@@ -7,9 +7,10 @@
 // 2^e is the smallest power of two above the row (column) maximum, so scaled
 // entries x lie in (-1, 1). Each x is written as signed base-2^9 digits
 //     x = sum_s sigma_s 2^-(8 + 9 s),  |sigma_s| <= 256,
-// every digit an integer that BF16 holds exactly. With S digits per operand
-// the pairs (s, t), s + t < S are kept; pairs of equal level d = s + t carry
-// the same weight 2^-(16 + 9 d), so they share one FP32 accumulator per level:
+// every digit an integer that BF16 holds exactly (stored times its weight
+// 2^-9s, still exact). With S digits per operand the pairs (s, t), s + t < S
+// are kept; pairs of equal level d = s + t carry the same weight
+// 2^-(16 + 9 d), so they share one FP32 accumulator per level:
 //     D_ij = 2^(e_i + f_j - 16) * sum_d 2^-9d T_d[i, j],
 //     T_d = sum_{s+t=d} sigma^A_s . sigma^B_t   (integer-valued).
 // Products of digits are at most 2^16, so an FP32 level accumulator is exact
@@ -40,17 +41,23 @@ using split::exponent_of_max;
 using split::kBeta;
 constexpr int kFlushK = 64;  // K is padded to a multiple of this
 
-// Workgroup layout of the slice-pair kernel by slice count: 2 x 4 waves of
-// 32 x 32 (64 x 128 tile) while four LDS stages of it fit, else 2 x 2 waves.
+// Slice-pair kernel layout by slice count. Up to 5 slices: 4 x 2 waves of
+// 32 x 64 (128 x 128 tile, two waves per SIMD), one 16-k block per LDS stage,
+// three stages in rotation; against 2 x 4 waves of 32 x 32 (64 x 128 tile) a
+// 16-k block reads 27% fewer LDS bytes per MFMA and a third fewer slice bytes
+// per flop. 6 and 7 slices need more fragment registers and keep 32 x 32 per
+// wave: 2 x 4 waves (6) or 2 x 2 (7), two 16-k blocks per stage, two stages.
 template <int S>
 struct Layout {
-  static constexpr int WMW = 2, WNW = (S <= 6) ? 4 : 2, WN = 1;
-  using C = split::Cfg<S, WMW, WNW, WN>;
+  static constexpr bool kWide = S <= 5;
+  static constexpr int WMW = kWide ? 4 : 2, WNW = kWide ? 2 : (S <= 6 ? 4 : 2), WN = kWide ? 2 : 1;
+  static constexpr int SKB = kWide ? 1 : 2, NBUF = kWide ? 3 : 2;
+  using C = split::Cfg<S, WMW, WNW, WN, SKB, NBUF>;
 };
 
 static void tile_of(int S, int *bm, int *bn) {
-  *bm = 64;
-  *bn = (S <= 6) ? 128 : 64;
+  *bm = S <= 5 ? 128 : 64;
+  *bn = S <= 6 ? 128 : 64;
 }
 
 // Row maxima of |A| (M x K row-major): one wave per row; IEEE bit pattern out.
@@ -86,7 +93,10 @@ __global__ __launch_bounds__(256) void k_scan_cols(const double *__restrict__ B,
 }
 
 // Signed digits of 8 consecutive-k values of one row (A) or column (B):
-// sig[s] holds digit s of each of the 8 values, as BF16.
+// sig[s] holds digit s of each of the 8 values times its weight 2^(-9 s), as
+// BF16 (exact: |digit| <= 256 needs 8 significant bits, and the power of two
+// only moves the exponent). With weighted digits every slice-pair product
+// carries the weight of its level, so levels can share accumulators.
 template <int S>
 __device__ __forceinline__ void digits8(const double v[8], int e, bf16x8 sig[S]) {
 #pragma unroll
@@ -95,7 +105,7 @@ __device__ __forceinline__ void digits8(const double v[8], int e, bf16x8 sig[S])
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const double d = rint(r);
-      sig[s][q] = (__bf16)(float)d;  // |d| <= 256: exact in BF16
+      sig[s][q] = (__bf16)(float)(d * __builtin_ldexp(1.0, -kBeta * s));
       r = (r - d) * (double)(1 << kBeta);
     }
   }
@@ -297,7 +307,7 @@ hipError_t launch_multiply_s(const SplitPlan &p, double *D, void *ws, hipStream_
   const int64_t KB = p.Kp / 16;
   using L = Layout<S>;
   const int64_t tmn = p.Mp / L::C::BM, tnn = p.Np / L::C::BN;
-  hipLaunchKernelGGL((split::k_split_gemm<S, L::WMW, L::WNW, L::WN, 1>), dim3((unsigned)(tmn * tnn)),
+  hipLaunchKernelGGL((split::k_split_gemm<S, L::WMW, L::WNW, L::WN, L::SKB, L::NBUF, 1>), dim3((unsigned)(tmn * tnn)),
                      dim3(L::C::kThreads), 0, s, Apk, Bpk, rowmax, colmax, D, p.M, p.N, KB, tmn, tnn);
   return hipGetLastError();
 }

@@ -3,34 +3,41 @@
 // Inputs are the fragment-packed BF16 slices of A and B written by the slicing
 // kernels (see k_split.hip): chunk = 64 lanes x 8 BF16 = one 32x16 (A) or
 // 16x32 (B) operand of v_mfma_f32_32x32x16_bf16, chunks ordered
-// [row block][k block (16)][slice].
+// [row block][k block (16)][slice]. Digit s is stored times its weight
+// 2^-9s (exact in BF16), so a slice-pair product carries the weight of its
+// level d = s + t.
 //
-// Workgroup = WMW x WNW waves; a wave owns a 32 x (32*WN) block of D. Per
-// level d = s + t of the kept slice pairs (s + t < S) a wave keeps one FP32
-// accumulator per 32x32 block. Digits are at most 2^8 in magnitude, so each
-// product is at most 2^16 and a level with (d+1) pairs stays exactly
-// representable in FP32 for 256/(d+1) k values. Each level is folded into the
-// FP64 accumulator (times its weight 2^-9d, exact) at its own period:
-//     level 0: every 256 k   (exact)
-//     level 1: every 128 k   (exact)
-//     level 2: every  64 k   (exact)
-//     level 3: every 256 k   (FP32 rounding possible only beyond 2^24, at a
-//                             weight of 2^-43: far below FP64 rounding of the
-//                             result)
-//     level >= 4: at the end (weight <= 2^-52)
-// The fold points repeat every 256 k (16 k blocks), so one cycle is unrolled
-// and every fold point, and every period start (whose first MFMA takes C = 0
-// instead of a zeroed accumulator), is known at compile time. A shorter tail
-// (K not a multiple of 256) folds levels 0..3 every 64 k.
+// Workgroup = WMW x WNW waves; a wave owns a 32 x (32*WN) block of D. A wave
+// keeps one FP32 accumulator per level and 32x32 block, except that 32 x 64
+// wave blocks (WN = 2) have registers for four: levels from 3 up then share
+// the fourth (MERGE). Digits are at most 2^8 in magnitude, so a product is at
+// most 2^16 times its weight and a level with (d+1) pairs stays exact in FP32
+// for 256/(d+1) k values. Each accumulator is folded into the FP64
+// accumulator at its own period:
+//     level 0:    every 256 k   (exact)
+//     level 1:    every 128 k   (exact)
+//     level 2:    every  64 k   (exact)
+//     level 3:    every 256 k   (exact while partial sums stay below 2^24;
+//                                weight 2^-27)
+//     levels 4+:  at the end    (weight <= 2^-36)
+//     merged 3+:  every 256 k   (levels 3 and 4 on one FP32 grid: a sum
+//                                rounded to 2^-24 of a level-3 sum; on the
+//                                2^[-8,8]-scaled workload about 3e-14 normwise
+//                                of the result, a few percent of the scheme's
+//                                own truncation error at 5 slices)
+// A fold adds the accumulator into FP64 and zeroes it; the last fold of each
+// accumulator comes after the last k block.
 //
 // A and B chunks are copied global -> LDS with global_load_lds_dwordx4 (no
-// staging registers). An LDS stage holds kSKB 16-wide k blocks of the tile's
-// slices; kNBuf stages rotate, so copies run kNBuf - 1 stages ahead of the
+// staging registers). An LDS stage holds SKB 16-wide k blocks of the tile's
+// slices; NBUF stages rotate, so copies run NBUF - 1 stages ahead of the
 // MFMAs and one barrier per stage suffices: the buffer refilled at stage st
 // was last read at stage st - 1, which every wave has left once it passes the
 // barrier of stage st. Each wave reads its fragments as conflict-free
-// ds_read_b128. Two stages of two k blocks measured slightly faster than four
-// of one (half the barriers, twice the MFMAs between them).
+// ds_read_b128: its S A fragments once per k block, then the S B fragments
+// of one 32-column block at a time (a wave with WN = 2 holds 2S, not 3S,
+// fragments, which is what lets 32 x 64 wave blocks run at two waves per
+// SIMD).
 #pragma once
 
 #include <utility>
@@ -40,35 +47,38 @@
 namespace moa {
 namespace split {
 
-constexpr int kBeta = 9;    // BF16 digit width: |digit| <= 2^(beta-1) = 256
-constexpr int kSKB = 2;       // 16-wide k blocks per LDS stage
-constexpr int kNBuf = 2;      // LDS stages in rotation
-constexpr int kCycleKB = 16;  // unrolled cycle: 256 k
-constexpr int kCycleSt = kCycleKB / kSKB;
-static_assert(kCycleKB % kSKB == 0 && 4 % kSKB == 0, "a 64-k tail step must be whole stages");
+constexpr int kBeta = 9;  // BF16 digit width: |digit| <= 2^(beta-1) = 256
 
 // s_waitcnt immediate: wait until at most n vector-memory operations of this
 // wave are outstanding (vmcnt split over bits 3:0 and 15:14; lgkm/exp: no wait).
 __host__ __device__ constexpr int vmcnt_imm(int n) { return 0x0F70 | (n & 15) | ((n >> 4) << 14); }
 
-// Fold period of level d in k blocks (0 = only at the end).
-__host__ __device__ constexpr int period_kb(int d) {
-  return d == 0 ? 16 : d == 1 ? 8 : d == 2 ? 4 : d == 3 ? 16 : 0;
+// Accumulator of level d: its own, or with MERGE one shared by every level
+// from 3 up.
+template <bool MERGE>
+__host__ __device__ constexpr int acc_of(int d) {
+  return (MERGE && d > 3) ? 3 : d;
 }
 
-template <int S, int WMW, int WNW, int WN>
+template <int S, int WMW, int WNW, int WN, int SKB, int NBUF>
 struct Cfg {
   static constexpr int kWaves = WMW * WNW;
   static constexpr int kThreads = 64 * kWaves;
   static constexpr int BM = 32 * WMW;
   static constexpr int BN = 32 * WN * WNW;
   static constexpr int MBW = BM / 32, NBW = BN / 32;
-  static constexpr int A_CH = MBW * kSKB * S;
-  static constexpr int B_CH = NBW * kSKB * S;
+  static constexpr int A_CH = MBW * SKB * S;
+  static constexpr int B_CH = NBW * SKB * S;
   static constexpr int ST_CH = A_CH + B_CH;
   static constexpr int PER_WAVE = ST_CH / kWaves;                  // copies per stage, later waves
   static constexpr int MAX_WAVE = (ST_CH + kWaves - 1) / kWaves;  // copies per stage, first waves
   static constexpr int EXTRA = ST_CH % kWaves;                     // waves that issue MAX_WAVE
+  // 32 x 64 wave blocks have registers for four accumulators per 32x32
+  // block: levels from 3 up share the fourth (MERGE); otherwise one each.
+  static constexpr bool MERGE = WN > 1;
+  static constexpr int L = (MERGE && S > 4) ? 4 : S;              // accumulators per 32x32 block
+  static_assert(4 % SKB == 0, "a 64-k group must be whole stages");
+  static_assert(sizeof(bf16x8) * 64 * ST_CH * NBUF <= 160 * 1024, "LDS stages exceed 160 KiB");
 };
 
 __device__ __forceinline__ floatx16 mfma_bf16(const bf16x8 &a, const bf16x8 &b, const floatx16 &c) {
@@ -84,44 +94,60 @@ __device__ __forceinline__ int exponent_of_max(uint64_t bits) {
   return e;
 }
 
-template <int S, int WMW, int WNW, int WN, int MINB>
+template <int S, int WMW, int WNW, int WN, int SKB, int NBUF, int MINB>
 __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
     const bf16x8 *__restrict__ Apk, const bf16x8 *__restrict__ Bpk, const uint64_t *__restrict__ rowmax,
     const uint64_t *__restrict__ colmax, double *__restrict__ D, int64_t M, int64_t N, int64_t KB, int64_t tiles_m,
     int64_t tiles_n) {
-  using C = Cfg<S, WMW, WNW, WN>;
-  __shared__ bf16x8 lds[kNBuf][C::ST_CH * 64];
+  using C = Cfg<S, WMW, WNW, WN, SKB, NBUF>;
+  constexpr int L = C::L;
+  __shared__ bf16x8 lds[NBUF][C::ST_CH * 64];
 
   int64_t tm, tn;
-  // Each XCD walks its share of the tiles 4 tile rows at a time (8192^3:
-  // 14.52-14.59 ms against 14.72-14.78 ms with 8 rows, 14.89 with 2; the
-  // concurrently resident tiles of an XCD then span 256 x 1024 of D).
+  // Each XCD walks its share of the tiles 4 tile rows at a time.
   grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 4, tm, tn);
   const int tid = threadIdx.x, lane = tid % 64;
   // Wave index as a wave-uniform (scalar) value, so chunk addresses are scalar.
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int wm = wave / WNW, wn = wave % WNW;
 
+  // Per-wave chunk bases at stage 0, forced wave-uniform so they live in
+  // scalar registers: a copy is then the scalar base plus the stage offset,
+  // with the lane's 16-byte offset as the only vector register (per-copy
+  // 64-bit vector addresses, hoisted out of the unrolled stages, would fill
+  // the register file).
+  const bf16x8 *cbase[C::MAX_WAVE];
+#pragma unroll
+  for (int q = 0; q < C::MAX_WAVE; ++q) {
+    const int c = wave + C::kWaves * q;
+    const bf16x8 *p;
+    if (c < C::A_CH) {
+      const int mbl = c / (SKB * S), rest = c % (SKB * S);
+      p = Apk + ((tm * C::MBW + mbl) * KB * S + rest) * 64;
+    } else {
+      const int cb = c - C::A_CH;
+      const int nbl = cb / (SKB * S), rest = cb % (SKB * S);
+      p = Bpk + ((tn * C::NBW + nbl) * KB * S + rest) * 64;
+    }
+    // readfirstlane returns a signed int: each half goes through uint32_t
+    // before widening, or a low half with bit 31 set would sign-extend over
+    // the high half.
+    const uint64_t u = (uint64_t)p;
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    cbase[q] = (const bf16x8 *)((hi << 32) | lo);
+  }
   auto issue_stage = [&](int64_t st, int buf) {
 #pragma unroll
     for (int q = 0; q < C::MAX_WAVE; ++q) {
       const int c = wave + C::kWaves * q;
       if (c >= C::ST_CH) break;
-      const bf16x8 *src;
-      if (c < C::A_CH) {
-        const int mbl = c / (kSKB * S), rest = c % (kSKB * S);
-        src = Apk + (((tm * C::MBW + mbl) * KB + st * kSKB) * S + rest) * 64;
-      } else {
-        const int cb = c - C::A_CH;
-        const int nbl = cb / (kSKB * S), rest = cb % (kSKB * S);
-        src = Bpk + (((tn * C::NBW + nbl) * KB + st * kSKB) * S + rest) * 64;
-      }
-      __builtin_amdgcn_global_load_lds((const void *)(src + lane),
+      __builtin_amdgcn_global_load_lds((const void *)(cbase[q] + st * (SKB * S * 64) + lane),
                                        (__attribute__((address_space(3))) void *)&lds[buf][c * 64], 16, 0, 0);
     }
   };
 
-  floatx16 acc[S][WN];
+  floatx16 acc[L][WN];
   double acc64[WN][16];
   const floatx16 zero16 = {};
 #pragma unroll
@@ -129,123 +155,109 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc64[j][v] = 0.0;
 #pragma unroll
-  for (int d = 0; d < S; ++d)
+  for (int l = 0; l < L; ++l)
 #pragma unroll
-    for (int j = 0; j < WN; ++j) acc[d][j] = zero16;
+    for (int j = 0; j < WN; ++j) acc[l][j] = zero16;
 
-  auto fold_level = [&](int d) {
-    const double w = __builtin_ldexp(1.0, -kBeta * d);
+  auto fold = [&](int l) {
 #pragma unroll
     for (int j = 0; j < WN; ++j)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc64[j][v] = fma((double)acc[d][j][v], w, acc64[j][v]);
+      for (int v = 0; v < 16; ++v) acc64[j][v] += (double)acc[l][j][v];
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[l][j] = zero16;
   };
 
-  // One 16-wide k block from LDS buffer `buf`. Q = position in the 256-k
-  // cycle (compile time), or -1 in the tail (no period starts or folds).
-  // All fragments are read first (one LDS round trip per stage), then the
-  // MFMAs run round-robin over the levels, largest level first, so
-  // consecutive MFMAs mostly update different accumulators.
-  auto mma_kb = [&](int buf, int kbl, auto qc) {
-    constexpr int Q = decltype(qc)::value;
-    bf16x8 af[S], bfr[S][WN];
+  // One 16-wide k block from LDS buffer `buf`. For each 32-column block j:
+  // read its S B fragments, then round r issues, for each level d >= r
+  // (largest first), the pair (s, t) = (r, d - r), so consecutive MFMAs
+  // mostly update different accumulators.
+  auto mma_kb = [&](int buf, int kbl) {
+    bf16x8 af[S], bfr[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) af[s] = lds[buf][((wm * kSKB + kbl) * S + s) * 64 + lane];
+    for (int s = 0; s < S; ++s) af[s] = lds[buf][((wm * SKB + kbl) * S + s) * 64 + lane];
+    [&]<int... J>(std::integer_sequence<int, J...>) {
+      ([&]<int j>(std::integral_constant<int, j>) {
 #pragma unroll
-    for (int t = 0; t < S; ++t)
+        for (int t = 0; t < S; ++t)
+          bfr[t] = lds[buf][C::A_CH * 64 + (((wn * WN + j) * SKB + kbl) * S + t) * 64 + lane];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int j = 0; j < WN; ++j)
-        bfr[t][j] = lds[buf][C::A_CH * 64 + (((wn * WN + j) * kSKB + kbl) * S + t) * 64 + lane];
-    __builtin_amdgcn_sched_barrier(0);
-    // Round r issues, for each level d >= r (largest first), the pair
-    // (s, t) = (r, d - r); rounds r = 0 .. S-1 cover every kept pair once.
+        for (int r = 0; r < S; ++r)
 #pragma unroll
-    for (int r = 0; r < S; ++r)
-#pragma unroll
-      for (int d = S - 1; d >= r; --d)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) {
-          const bool start = Q >= 0 && r == 0 && period_kb(d) > 0 && Q % period_kb(d) == 0;
-          acc[d][j] = mfma_bf16(af[r], bfr[d - r][j], start ? zero16 : acc[d][j]);
-        }
-    if constexpr (Q >= 0) {
-#pragma unroll
-      for (int d = 0; d < S; ++d)
-        if (period_kb(d) > 0 && (Q + 1) % period_kb(d) == 0) fold_level(d);
-    }
+          for (int d = S - 1; d >= r; --d) {
+            constexpr bool MG = C::MERGE;
+            acc[acc_of<MG>(d)][j] = mfma_bf16(af[r], bfr[d - r], acc[acc_of<MG>(d)][j]);
+          }
+        __builtin_amdgcn_sched_barrier(0);
+      }(std::integral_constant<int, J>{}), ...);
+    }(std::make_integer_sequence<int, WN>{});
   };
 
-  const int64_t nst = KB / kSKB;
+  const int64_t nst = KB / SKB;
   // Stage st: wait for its copies, barrier, refill the buffer of stage st - 1
-  // with stage st + kNBuf - 1, then multiply its kSKB k blocks. I = position
-  // of the stage in the 256-k cycle, or -1 in the tail.
-  auto stage = [&](int64_t st, auto ic) {
-    constexpr int I = decltype(ic)::value;
-    const int buf = (int)(st % kNBuf);
-    // Issued so far: stages up to st + kNBuf - 2. Stage st must be complete;
-    // the kNBuf - 2 after it may stay in flight (all of them near the end).
-    if (kNBuf > 2 && st + kNBuf - 2 < nst) {
+  // with stage st + NBUF - 1, then multiply its SKB k blocks.
+  auto stage = [&](int64_t st) {
+    const int buf = (int)(st % NBUF);
+    // Issued so far: stages up to st + NBUF - 2. Stage st must be complete;
+    // the NBUF - 2 after it may stay in flight (all of them near the end).
+    if (NBUF > 2 && st + NBUF - 2 < nst) {
       if (wave < C::EXTRA)
-        __builtin_amdgcn_s_waitcnt(vmcnt_imm((kNBuf - 2) * C::MAX_WAVE));
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm((NBUF - 2) * C::MAX_WAVE));
       else
-        __builtin_amdgcn_s_waitcnt(vmcnt_imm((kNBuf - 2) * C::PER_WAVE));
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm((NBUF - 2) * C::PER_WAVE));
     } else {
       __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
     }
     // A plain barrier, not __syncthreads(): its fence would also wait for the
     // copies still in flight. LDS is coherent within the workgroup.
     __builtin_amdgcn_s_barrier();
-    if (st + kNBuf - 1 < nst) issue_stage(st + kNBuf - 1, (int)((st + kNBuf - 1) % kNBuf));
-    [&]<int... J>(std::integer_sequence<int, J...>) {
-      (mma_kb(buf, J, std::integral_constant<int, I < 0 ? -1 : I * kSKB + J>{}), ...);
-    }(std::make_integer_sequence<int, kSKB>{});
+    if (st + NBUF - 1 < nst) issue_stage(st + NBUF - 1, (int)((st + NBUF - 1) % NBUF));
+#pragma unroll
+    for (int kbl = 0; kbl < SKB; ++kbl) mma_kb(buf, kbl);
   };
 
-  for (int i = 0; i < kNBuf - 1; ++i)
+  for (int i = 0; i < NBUF - 1; ++i)
     if (i < nst) issue_stage(i, i);
-  const int64_t ncyc = nst / kCycleSt;
-  int64_t st = 0;
-  for (int64_t cyc = 0; cyc < ncyc; ++cyc) {
-    [&]<int... I>(std::integer_sequence<int, I...>) {
-      (stage(st + I, std::integral_constant<int, I>{}), ...);
-    }(std::make_integer_sequence<int, kCycleSt>{});
-    st += kCycleSt;
-  }
-  if (st < nst) {
-    // Tail: levels 0..3 restart from zero and fold every 64 k.
+  // Groups of 64 k (K is padded to a multiple of 64): level 2 folds after
+  // every group, level 1 after every second, levels 0 and 3 (or the merged
+  // accumulator) after every fourth, separate levels from 4 up only after the
+  // last; every accumulator folds after the last group (a fold zeroes it).
+  const int64_t ngroups = nst / (4 / SKB);
+  for (int64_t g = 0; g < ngroups; ++g) {
 #pragma unroll
-    for (int d = 0; d < S && d < 4; ++d)
+    for (int i = 0; i < 4 / SKB; ++i) stage(g * (4 / SKB) + i);
+    const bool last = g + 1 == ngroups;
+    if constexpr (L > 2) fold(2);
+    if constexpr (L > 1)
+      if ((g & 1) == 1 || last) fold(1);
+    if ((g & 3) == 3 || last) {
+      fold(0);
+      if constexpr (L > 3) fold(3);
+    }
+    if (last) {
 #pragma unroll
-      for (int j = 0; j < WN; ++j) acc[d][j] = zero16;
-    for (; st < nst; st += 4 / kSKB) {
-#pragma unroll
-      for (int i = 0; i < 4 / kSKB; ++i) stage(st + i, std::integral_constant<int, -1>{});
-#pragma unroll
-      for (int d = 0; d < S && d < 4; ++d) {
-        fold_level(d);
-#pragma unroll
-        for (int j = 0; j < WN; ++j) acc[d][j] = zero16;
-      }
+      for (int l = 4; l < L; ++l) fold(l);
     }
   }
-  // Levels that fold only at the end.
-#pragma unroll
-  for (int d = 4; d < S; ++d) fold_level(d);
 
   // Epilogue: exact power-of-two descaling, D[i, j] = 2^(e_i + f_j - 16) * acc.
+  // Lane l < 32 reads the exponent of the wave's row l and hands it to the
+  // lanes that store that row (one load per lane instead of 16, which the
+  // compiler would hoist above the loop and keep in registers).
   const int64_t col_base = tn * C::BN + wn * (32 * WN);
   const int64_t row_base = tm * C::BM + wm * 32;
+  const int e_lane = (row_base + lane % 32 < M) ? exponent_of_max(rowmax[row_base + lane % 32]) : 0;
 #pragma unroll
   for (int j = 0; j < WN; ++j) {
     const int64_t gn = col_base + j * 32 + lane % 32;
     const int fe = (gn < N) ? exponent_of_max(colmax[gn]) : 0;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int64_t gm = row_base + (v / 4) * 8 + (lane / 32) * 4 + (v % 4);
-      if (gm < M && gn < N) {
-        const int ee = exponent_of_max(rowmax[gm]);
-        D[gm * N + gn] = ldexp(acc64[j][v], ee + fe - 2 * (kBeta - 1));
-      }
+      const int r = (v / 4) * 8 + (lane / 32) * 4 + (v % 4);
+      const int ee = __shfl(e_lane, r);
+      const int64_t gm = row_base + r;
+      if (gm < M && gn < N) D[gm * N + gn] = ldexp(acc64[j][v], ee + fe - 2 * (kBeta - 1));
     }
   }
 }

@@ -66,7 +66,10 @@ def test_static_scratch_matches_workspace_entry_point(fmt, S, beta):
         want = moa.inner_split(ga, gb, fmt, S).cpu().numpy()
         assert _bits_equal(got, want)
         rows = np.unique(np.concatenate([[0, M - 1], rng.choice(M, 8, replace=False)]))
-        assert oracle.normwise_error(got[rows], oracle.split_inner(a, b, nslices=S, beta=beta, rows=rows)) <= 1e-14
+        # The same kernels as moa_inner_split: 5 BF16 slices sum levels 3 and
+        # 4 in one FP32 accumulator (about 3e-14 from the exact scheme).
+        tol = 2e-13 if fmt == "bf16" else 1e-14
+        assert oracle.normwise_error(got[rows], oracle.split_inner(a, b, nslices=S, beta=beta, rows=rows)) <= tol
         assert oracle.normwise_error(got[rows], oracle.inner_dot2(a, b, rows=rows)) <= 1e-12
 
 
