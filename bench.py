@@ -486,7 +486,45 @@ def main():
                   "product_kernel_tops": round(int8_ops, 2), "frac_int8_peak": round(int8_ops / 5033.2, 4)}
     log("bench: int8 split %.3f ms/step, %.1f Gop/s, rel diff %.2e" %
         (split_int8["ms_per_step"], split_int8["value"], diff8))
-    del dp, d8, ws8
+
+    # The FP8 (E4M3) slice variant on the same inputs (10 slices of 5-bit digits).
+    SF = 10
+    wsf = torch.empty(moa.split_workspace_bytes(a.shape, b.shape, "fp8", SF), dtype=torch.uint8, device=dev)
+    df = torch.empty_like(d)
+
+    def stepf(ev=None):
+        if ev is not None:
+            ev[0].record()
+        moa.split_prepare(a, b, wsf, "fp8", SF)
+        if ev is not None:
+            ev[1].record()
+        moa.split_multiply(a.shape, b.shape, df, wsf, "fp8", SF)
+        if ev is not None:
+            ev[2].record()
+
+    for _ in range(max(1, args.warmup)):
+        stepf()
+    torch.cuda.synchronize()
+    evsf = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        stepf(evsf[i])
+    torch.cuda.synchronize()
+    elf = time.perf_counter() - t0
+    multf = sum(e[1].elapsed_time(e[2]) for e in evsf) / args.steps
+    prepf = sum(e[0].elapsed_time(e[1]) for e in evsf) / args.steps
+    difff = float(torch.linalg.norm(df[rows] - dp[rows]) / torch.linalg.norm(dp[rows]))
+    f8_tflops = SF * (SF + 1) // 2 * ops / (multf * 1e-3) / 1e12
+    split_fp8 = {"value": round(ops * args.steps / elf / 1e9, 3), "unit": "Gop/s",
+                 "ms_per_step": round(elf * 1e3 / args.steps, 4),
+                 "stages_ms": {"prepare": round(prepf, 4), "multiply": round(multf, 4)},
+                 "slices": SF, "slice_pairs": SF * (SF + 1) // 2, "rel_diff_vs_plain": difff,
+                 "product_kernel_tflops": round(f8_tflops, 2), "frac_fp8_peak": round(f8_tflops / 5033.2, 4)}
+    log("bench: fp8 split %.3f ms/step, %.1f Gop/s, rel diff %.2e" %
+        (split_fp8["ms_per_step"], split_fp8["value"], difff))
+    sampled["split_fp8"] = df[er].cpu().numpy()
+    del wsf, df
+    del d8, ws8
 
     result = {
         "metric": METRIC,
@@ -509,6 +547,7 @@ def main():
                        "frac_fp64_peak": round(plain_gops / 1e3 / PEAK_FP64_TFLOPS, 4)},
         "split_vs_plain": round(value / plain_gops, 4),
         "split_int8": split_int8,
+        "split_fp8": split_fp8,
         "rel_diff_split_vs_plain": diff,
         "roofline": {"bound": "mfma", "kernel": "k_split_gemm<%d>" % S, "achieved": round(achieved, 2),
                      "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
@@ -520,7 +559,7 @@ def main():
         log("bench: error against the oracle on %d sampled rows" % len(err_rows))
         errs = oracle_errors(a_h, b_h, sampled, err_rows)
         bound = 1e-12
-        ok = all(errs[k]["normwise"] <= bound for k in ("split_bf16", "split_int8"))
+        ok = all(errs[k]["normwise"] <= bound for k in ("split_bf16", "split_int8", "split_fp8"))
         result["error_vs_oracle"] = dict(errs, reference="oracle Dot2 (compensated FP64)",
                                          rows=len(err_rows), bound_normwise=bound, within_bound=ok)
         if not ok:

@@ -169,13 +169,15 @@ moa_status moa_outer(moa_shape sa, const void *A, moa_shape sb, const void *B, m
  * bits, each digit an integer the slice format holds exactly
  * (MOA_SPLIT_BF16: beta = 9, |digit| <= 256, FP32 accumulation, exact for the
  * leading weights; MOA_SPLIT_INT8: beta = 7, |digit| <= 64, INT32
- * accumulation, exact; MOA_SPLIT_FP8 is reserved and not built). The slice
- * pairs (s, t) with s + t < nslices are multiplied on the matrix cores,
- * summed in FP64 and scaled back exactly.
- * Requirements: finite inputs; 1 <= nslices <= MOA_SPLIT_MAX_SLICES.
+ * accumulation, exact; MOA_SPLIT_FP8: E4M3 digits, beta = 5, |digit| <= 16,
+ * FP32 accumulation, exact). The slice pairs (s, t) with s + t < nslices are
+ * multiplied on the matrix cores, summed in FP64 and scaled back exactly.
+ * Requirements: finite inputs; 1 <= nslices <= 7 (BF16, INT8) or 10 (FP8)
+ * (MOA_SPLIT_MAX_SLICES is the largest of these).
  * Accuracy (entries u*2^k with k in [-8, 8], K = 8192), normwise relative
  * error against an exactly rounded product: BF16, nslices = 5 (15 pairs):
- * about 7e-13; INT8, nslices = 7 (28 pairs): about 5e-14.
+ * about 7e-13; INT8, nslices = 7 (28 pairs): about 5e-14; FP8, nslices = 9
+ * (45 pairs): about 8e-13, nslices = 10 (55 pairs): about 3e-14.
  *
  * ws: device workspace of at least moa_inner_split_workspace(...) bytes, owned
  * by the caller, 256-byte aligned; contents on entry are ignored.
@@ -183,7 +185,7 @@ moa_status moa_outer(moa_shape sa, const void *A, moa_shape sb, const void *B, m
 #define MOA_SPLIT_BF16 0
 #define MOA_SPLIT_FP8 1
 #define MOA_SPLIT_INT8 2
-#define MOA_SPLIT_MAX_SLICES 7
+#define MOA_SPLIT_MAX_SLICES 10
 size_t moa_inner_split_workspace(moa_shape sa, moa_shape sb, int32_t fmt, int32_t nslices);
 moa_status moa_inner_split(moa_shape sa, const double *A, moa_shape sb, const double *B, double *D, int32_t fmt,
                            int32_t nslices, void *ws, size_t ws_bytes, void *stream);

@@ -64,6 +64,8 @@ struct SplitPlan {
   int fmt, S, beta;
   size_t off_ea, off_fb, off_ap, off_bp, total;
 };
+// Largest slice count of a split format (0 for an unknown format).
+int split_max_slices(int fmt);
 bool split_plan(int64_t M, int64_t K, int64_t N, int fmt, int S, SplitPlan *p);
 hipError_t launch_split_prepare(const SplitPlan &p, const double *A, const double *B, void *ws, hipStream_t s);
 hipError_t launch_split_multiply(const SplitPlan &p, double *D, void *ws, hipStream_t s);

@@ -131,21 +131,51 @@ __device__ __forceinline__ void digits16_i8(const double v[16], int e, split::i8
   }
 }
 
+// FP8 slices (MOA_SPLIT_FP8): signed digits of 5 bits, |digit| <= 16, each
+// an E4M3 value exactly (4 significant bits); chunk = 64 lanes x 32 FP8 (a
+// 32 x 64 operand of v_mfma_scale_f32_32x32x64_f8f6f4, lane l holding
+// row/col l % 32 and k = 32 * (l / 32) .. + 31), stored as two 1-KiB halves
+// (lane l's bytes 0-15, then its bytes 16-31) so each half is one
+// 16-byte-per-lane copy. sig[s][h]: the 16 digits of slice s in half h.
+template <int S>
+__device__ __forceinline__ void digits32_f8(const double v[32], int e, split::f8::intx4 sig[S][2]) {
+  constexpr int kB = split::f8::kBeta;
+#pragma unroll
+  for (int s = 0; s < S; ++s) sig[s][0] = sig[s][1] = split::f8::intx4{0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 32; q += 2) {
+    double r0 = ldexp(v[q], kB - 1 - e), r1 = ldexp(v[q + 1], kB - 1 - e);  // x * 2^(beta-1), exact
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double d0 = rint(r0), d1 = rint(r1);
+      // Two digits into bytes 0-1 (q % 4 == 0) or 2-3 of the dword; exact.
+      const int old = sig[s][q / 16][(q % 16) / 4];
+      const int w = (q % 4 == 0) ? __builtin_amdgcn_cvt_pk_fp8_f32((float)d0, (float)d1, 0, false)
+                                 : __builtin_amdgcn_cvt_pk_fp8_f32((float)d0, (float)d1, old, true);
+      sig[s][q / 16][(q % 16) / 4] = w;
+      r0 = (r0 - d0) * (double)(1 << kB);
+      r1 = (r1 - d1) * (double)(1 << kB);
+    }
+  }
+}
+
 // A slices. A wave owns one chunk: row block mb (32 rows) and k block kb (CK =
-// 16 k for BF16, 32 for INT8). It copies the chunk's block of A into its own
+// 16 k for BF16, 32 for INT8, 64 for FP8). It copies the chunk's block of A into its own
 // LDS region with row-contiguous loads (CK lanes per row, 64 / CK rows per
 // load), then each lane reads back the values of its operand slot (row l % 32,
 // k = CK / 2 * (l / 32) ..) and writes their digits. Loading A directly in the
 // operand layout would make every load instruction touch 64 rows. The INT8
 // block (32 x 32) is staged 16 rows at a time, so the LDS a workgroup needs
 // stays small enough for 8 waves per SIMD (32 rows at once: 0.272 ms, 16 at a
-// time: 0.231 ms at 8192^2).
-template <int S, bool I8>
+// time: 0.231 ms at 8192^2); the FP8 block (32 x 64) likewise.
+// F: slice format, 0 = BF16, 1 = INT8, 2 = FP8.
+template <int S, int F>
 __global__ __launch_bounds__(256) void k_slice_a(const double *__restrict__ A, int64_t M, int64_t K,
                                                  const uint64_t *__restrict__ rowmax, int64_t KB, int64_t nchunks,
                                                  void *__restrict__ Apk) {
-  constexpr int CK = I8 ? 32 : 16, VL = CK / 2, RPL = kWave / CK;
-  constexpr int ROWS = I8 ? 16 : 32;  // rows staged per pass
+  constexpr bool I8 = F == 1, F8 = F == 2;
+  constexpr int CK = F8 ? 64 : I8 ? 32 : 16, VL = CK / 2, RPL = kWave / CK;
+  constexpr int ROWS = (I8 || F8) ? 16 : 32;  // rows staged per pass
   constexpr int LS = CK + 2;          // padded row stride (doubles) of the staged block
   __shared__ double tile[4][ROWS * LS];
   const int lane = threadIdx.x % kWave;
@@ -158,6 +188,7 @@ __global__ __launch_bounds__(256) void k_slice_a(const double *__restrict__ A, i
   const int e = live ? exponent_of_max(rowmax[mb * 32 + r]) : 0;
   [[maybe_unused]] split::i8::intx4 sig8[S];
   [[maybe_unused]] bf16x8 sig16[S];
+  [[maybe_unused]] split::f8::intx4 sigf[S][2];
 #pragma unroll
   for (int pass = 0; pass < 32 / ROWS; ++pass) {
     if (live) {
@@ -175,7 +206,9 @@ __global__ __launch_bounds__(256) void k_slice_a(const double *__restrict__ A, i
       double v[VL];
 #pragma unroll
       for (int q = 0; q < VL; ++q) v[q] = T[(r % ROWS) * LS + h * VL + q];
-      if constexpr (I8)
+      if constexpr (F8)
+        digits32_f8<S>(v, e, sigf);
+      else if constexpr (I8)
         digits16_i8<S>(v, e, sig8);
       else
         digits8<S>(v, e, sig16);
@@ -183,7 +216,14 @@ __global__ __launch_bounds__(256) void k_slice_a(const double *__restrict__ A, i
     if (pass + 1 < 32 / ROWS) __syncthreads();  // the block is refilled next pass
   }
   if (!live) return;
-  if constexpr (I8) {
+  if constexpr (F8) {
+    split::f8::intx4 *dst = (split::f8::intx4 *)Apk + (blk * S) * 128 + lane;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      dst[s * 128] = sigf[s][0];
+      dst[s * 128 + 64] = sigf[s][1];
+    }
+  } else if constexpr (I8) {
     split::i8::intx4 *dst = (split::i8::intx4 *)Apk + (blk * S) * 64 + lane;
 #pragma unroll
     for (int s = 0; s < S; ++s) dst[s * 64] = sig8[s];
@@ -238,7 +278,32 @@ __global__ __launch_bounds__(256) void k_slice_b_i8(const double *__restrict__ B
   for (int s = 0; s < S; ++s) dst[s * 64] = sig[s];
 }
 
-// Scans shared by both formats.
+// FP8 B slices: as k_slice_b with 64-k chunks of FP8 digits in two halves.
+template <int S>
+__global__ __launch_bounds__(256) void k_slice_b_f8(const double *__restrict__ B, int64_t K, int64_t N,
+                                                    const uint64_t *__restrict__ colmax, int64_t KB, int64_t nchunks,
+                                                    split::f8::intx4 *__restrict__ Bpk) {
+  const int64_t blk = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (blk >= nchunks) return;
+  const int lane = threadIdx.x % 64;
+  const int64_t nb = blk / KB, kb = blk % KB;
+  const int64_t col = nb * 32 + lane % 32;
+  const int64_t k0 = kb * 64 + (lane / 32) * 32;
+  double v[32];
+#pragma unroll
+  for (int q = 0; q < 32; ++q) v[q] = (col < N && k0 + q < K) ? B[(k0 + q) * N + col] : 0.0;
+  const int e = (col < N) ? exponent_of_max(colmax[col]) : 0;
+  split::f8::intx4 sig[S][2];
+  digits32_f8<S>(v, e, sig);
+  split::f8::intx4 *dst = Bpk + (blk * S) * 128 + lane;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    dst[s * 128] = sig[s][0];
+    dst[s * 128 + 64] = sig[s][1];
+  }
+}
+
+// Scans shared by every format.
 static void launch_scans(const SplitPlan &p, const double *A, const double *B, uint64_t *rowmax, uint64_t *colmax,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)((p.Mp + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, p.Mp);
@@ -258,7 +323,7 @@ hipError_t launch_prepare_i8(const SplitPlan &p, const double *A, const double *
   const int64_t KB = p.Kp / 32;
   launch_scans(p, A, B, rowmax, colmax, s);
   const int64_t cha = (p.Mp / 32) * KB, chb = (p.Np / 32) * KB;
-  hipLaunchKernelGGL((k_slice_a<S, true>), dim3((unsigned)((cha + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax,
+  hipLaunchKernelGGL((k_slice_a<S, 1>), dim3((unsigned)((cha + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax,
                      KB, cha, Apk);
   hipLaunchKernelGGL((k_slice_b_i8<S>), dim3((unsigned)((chb + 3) / 4)), dim3(256), 0, s, B, p.K, p.N, colmax, KB,
                      chb, Bpk);
@@ -281,6 +346,38 @@ hipError_t launch_multiply_i8(const SplitPlan &p, double *D, void *ws, hipStream
 }
 
 template <int S>
+hipError_t launch_prepare_f8(const SplitPlan &p, const double *A, const double *B, void *ws, hipStream_t s) {
+  char *w = (char *)ws;
+  uint64_t *rowmax = (uint64_t *)(w + p.off_ea);
+  uint64_t *colmax = (uint64_t *)(w + p.off_fb);
+  auto *Apk = (split::f8::intx4 *)(w + p.off_ap);
+  auto *Bpk = (split::f8::intx4 *)(w + p.off_bp);
+  const int64_t KB = p.Kp / 64;
+  launch_scans(p, A, B, rowmax, colmax, s);
+  const int64_t cha = (p.Mp / 32) * KB, chb = (p.Np / 32) * KB;
+  hipLaunchKernelGGL((k_slice_a<S, 2>), dim3((unsigned)((cha + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, KB,
+                     cha, Apk);
+  hipLaunchKernelGGL((k_slice_b_f8<S>), dim3((unsigned)((chb + 3) / 4)), dim3(256), 0, s, B, p.K, p.N, colmax, KB,
+                     chb, Bpk);
+  return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_multiply_f8(const SplitPlan &p, double *D, void *ws, hipStream_t s) {
+  char *w = (char *)ws;
+  const uint64_t *rowmax = (const uint64_t *)(w + p.off_ea);
+  const uint64_t *colmax = (const uint64_t *)(w + p.off_fb);
+  const auto *Apk = (const split::f8::intx4 *)(w + p.off_ap);
+  const auto *Bpk = (const split::f8::intx4 *)(w + p.off_bp);
+  const int64_t KB = p.Kp / 64;
+  using C = split::f8::Cfg<S, 2, 2>;
+  const int64_t tmn = p.Mp / C::BM, tnn = p.Np / C::BN;
+  hipLaunchKernelGGL((split::f8::k_split_gemm_f8<S, 2, 2>), dim3((unsigned)(tmn * tnn)), dim3(C::kThreads), 0, s,
+                     Apk, Bpk, rowmax, colmax, D, p.M, p.N, KB, tmn, tnn);
+  return hipGetLastError();
+}
+
+template <int S>
 hipError_t launch_prepare_s(const SplitPlan &p, const double *A, const double *B, void *ws, hipStream_t s) {
   char *w = (char *)ws;
   uint64_t *rowmax = (uint64_t *)(w + p.off_ea);
@@ -290,7 +387,7 @@ hipError_t launch_prepare_s(const SplitPlan &p, const double *A, const double *B
   const int64_t KB = p.Kp / 16;
   launch_scans(p, A, B, rowmax, colmax, s);
   const int64_t cha = (p.Mp / 32) * KB, chb = (p.Np / 32) * KB;
-  hipLaunchKernelGGL((k_slice_a<S, false>), dim3((unsigned)((cha + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, KB,
+  hipLaunchKernelGGL((k_slice_a<S, 0>), dim3((unsigned)((cha + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, KB,
                      cha, Apk);
   hipLaunchKernelGGL((k_slice_b<S>), dim3((unsigned)((chb + 3) / 4)), dim3(256), 0, s, B, p.K, p.N, colmax, KB, chb,
                      Bpk);
@@ -317,8 +414,12 @@ hipError_t launch_multiply_s(const SplitPlan &p, double *D, void *ws, hipStream_
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+int split_max_slices(int fmt) {
+  return fmt == MOA_SPLIT_FP8 ? 10 : (fmt == MOA_SPLIT_BF16 || fmt == MOA_SPLIT_INT8) ? 7 : 0;
+}
+
 bool split_plan(int64_t M, int64_t K, int64_t N, int fmt, int S, SplitPlan *p) {
-  if ((fmt != MOA_SPLIT_BF16 && fmt != MOA_SPLIT_INT8) || S < 1 || S > MOA_SPLIT_MAX_SLICES) return false;
+  if (S < 1 || S > split_max_slices(fmt)) return false;
   p->M = M;
   p->K = K;
   p->N = N;
@@ -330,11 +431,17 @@ bool split_plan(int64_t M, int64_t K, int64_t N, int fmt, int S, SplitPlan *p) {
     tile_of(S, &bm, &bn);
     p->Kp = round_up(K > 0 ? K : 1, kFlushK);
     bytes = 2;
-  } else {
+  } else if (fmt == MOA_SPLIT_INT8) {
     p->beta = split::i8::kBeta;
     bm = split::i8::Cfg<1, 2, 4>::BM;
     bn = split::i8::Cfg<1, 2, 4>::BN;
     p->Kp = round_up(K > 0 ? K : 1, 32);
+    bytes = 1;
+  } else {
+    p->beta = split::f8::kBeta;
+    bm = split::f8::Cfg<1, 2, 2>::BM;
+    bn = split::f8::Cfg<1, 2, 2>::BN;
+    p->Kp = round_up(K > 0 ? K : 1, 64);
     bytes = 1;
   }
   p->Mp = round_up(M > 0 ? M : 1, bm);
@@ -353,6 +460,21 @@ bool split_plan(int64_t M, int64_t K, int64_t N, int fmt, int S, SplitPlan *p) {
 }
 
 hipError_t launch_split_prepare(const SplitPlan &p, const double *A, const double *B, void *ws, hipStream_t s) {
+  if (p.fmt == MOA_SPLIT_FP8) {
+    switch (p.S) {
+      case 1: return launch_prepare_f8<1>(p, A, B, ws, s);
+      case 2: return launch_prepare_f8<2>(p, A, B, ws, s);
+      case 3: return launch_prepare_f8<3>(p, A, B, ws, s);
+      case 4: return launch_prepare_f8<4>(p, A, B, ws, s);
+      case 5: return launch_prepare_f8<5>(p, A, B, ws, s);
+      case 6: return launch_prepare_f8<6>(p, A, B, ws, s);
+      case 7: return launch_prepare_f8<7>(p, A, B, ws, s);
+      case 8: return launch_prepare_f8<8>(p, A, B, ws, s);
+      case 9: return launch_prepare_f8<9>(p, A, B, ws, s);
+      case 10: return launch_prepare_f8<10>(p, A, B, ws, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (p.fmt == MOA_SPLIT_INT8) {
     switch (p.S) {
       case 1: return launch_prepare_i8<1>(p, A, B, ws, s);
@@ -378,6 +500,21 @@ hipError_t launch_split_prepare(const SplitPlan &p, const double *A, const doubl
 }
 
 hipError_t launch_split_multiply(const SplitPlan &p, double *D, void *ws, hipStream_t s) {
+  if (p.fmt == MOA_SPLIT_FP8) {
+    switch (p.S) {
+      case 1: return launch_multiply_f8<1>(p, D, ws, s);
+      case 2: return launch_multiply_f8<2>(p, D, ws, s);
+      case 3: return launch_multiply_f8<3>(p, D, ws, s);
+      case 4: return launch_multiply_f8<4>(p, D, ws, s);
+      case 5: return launch_multiply_f8<5>(p, D, ws, s);
+      case 6: return launch_multiply_f8<6>(p, D, ws, s);
+      case 7: return launch_multiply_f8<7>(p, D, ws, s);
+      case 8: return launch_multiply_f8<8>(p, D, ws, s);
+      case 9: return launch_multiply_f8<9>(p, D, ws, s);
+      case 10: return launch_multiply_f8<10>(p, D, ws, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (p.fmt == MOA_SPLIT_INT8) {
     switch (p.S) {
       case 1: return launch_multiply_i8<1>(p, D, ws, s);

@@ -332,9 +332,8 @@ moa_status split_check(moa_shape sa, moa_shape sb, int32_t fmt, int32_t nslices,
                        moa::SplitPlan *p) {
   if (fmt != MOA_SPLIT_BF16 && fmt != MOA_SPLIT_FP8 && fmt != MOA_SPLIT_INT8)
     return fail(MOA_ERR_ARG, "unknown split format %d", fmt);
-  if (fmt == MOA_SPLIT_FP8) return fail(MOA_ERR_ARG, "FP8 slices are not built in this library");
-  if (nslices < 1 || nslices > MOA_SPLIT_MAX_SLICES)
-    return fail(MOA_ERR_ARG, "nslices %d outside [1, %d]", nslices, MOA_SPLIT_MAX_SLICES);
+  if (nslices < 1 || nslices > moa::split_max_slices(fmt))
+    return fail(MOA_ERR_ARG, "nslices %d outside [1, %d] for this format", nslices, moa::split_max_slices(fmt));
   moa_status st = flatten_inner(sa, sb, f);
   if (st != MOA_OK) return st;
   if (!moa::split_plan(f->M, f->K, f->N, fmt, nslices, p)) return fail(MOA_ERR_ARG, "split plan failed");

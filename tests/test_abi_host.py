@@ -128,12 +128,20 @@ def test_split_workspace_and_validation():
     assert moa.split_workspace_bytes((3, 5), (5, 2), "bf16", 9) == 0
     n8 = moa.split_workspace_bytes((8192, 8192), (8192, 8192), "int8", 7)
     assert 2 * 7 * 8192 * 8192 <= n8 < 2 * 7 * 8192 * 8192 + 4 * 8192 * 8 + 4096
+    # FP8: one byte per digit, up to 10 slices; BF16 and INT8 stop at 7.
+    nf = moa.split_workspace_bytes((8192, 8192), (8192, 8192), "fp8", 10)
+    assert 2 * 10 * 8192 * 8192 <= nf < 2 * 10 * 8192 * 8192 + 4 * 8192 * 8 + 4096
+    assert moa.split_workspace_bytes((3, 5), (5, 2), "fp8", 11) == 0
+    assert moa.split_workspace_bytes((3, 5), (5, 2), "int8", 8) == 0
+    assert moa.split_workspace_bytes((3, 5), (5, 2), "fp8", 8) > 0
     sh = moa._shape
     z = ctypes.c_void_p
     args = (sh((4, 8)), z(0x100000), sh((8, 2)), z(0x200000), z(0x300000))
     assert S[L.moa_inner_split(*args, 0, 0, z(0x400000), 1 << 20, z(0))] == "MOA_ERR_ARG"
     assert S[L.moa_inner_split(*args, 0, 8, z(0x400000), 1 << 20, z(0))] == "MOA_ERR_ARG"
     assert S[L.moa_inner_split(*args, 5, 5, z(0x400000), 1 << 20, z(0))] == "MOA_ERR_ARG"
+    assert S[L.moa_inner_split(*args, 1, 11, z(0x400000), 1 << 20, z(0))] == "MOA_ERR_ARG"   # FP8 > 10 slices
+    assert S[L.moa_inner_split(*args, 2, 8, z(0x400000), 1 << 20, z(0))] == "MOA_ERR_ARG"    # INT8 > 7 slices
     assert S[L.moa_inner_split(*args, 0, 5, z(0), 1 << 20, z(0))] == "MOA_ERR_WORKSPACE"
     assert S[L.moa_inner_split(*args, 0, 5, z(0x400000), 16, z(0))] == "MOA_ERR_WORKSPACE"
     assert S[L.moa_inner_split(*args, 0, 5, z(0x400010), 1 << 20, z(0))] == "MOA_ERR_WORKSPACE"

@@ -892,7 +892,7 @@ def test_split_two_stage_api_matches_one_call():
     a = mi.scaled_f64(rng, (200, 700))
     b = mi.scaled_f64(rng, (700, 150))
     ga, gb = gpu(a), gpu(b)
-    for fmt, S, beta in (("bf16", 5, 9), ("int8", 7, 7)):
+    for fmt, S, beta in (("bf16", 5, 9), ("int8", 7, 7), ("fp8", 9, 5)):
         say("split two-stage", fmt)
         one = host(G.inner_split(ga, gb, fmt, S))
         ws = torch.empty(moa.split_workspace_bytes(a.shape, b.shape, fmt, S), dtype=torch.uint8, device=DEV)
@@ -1093,7 +1093,7 @@ def test_fp32_batch_exact_integers_32bit_index():
 # FP64 in the middle of the loop (every 8192 k), the BF16 kernel runs a
 # 64-k tail after its unrolled 256-k cycles.
 
-@pytest.mark.parametrize("fmt,S,beta", [("bf16", 5, 9), ("int8", 7, 7)])
+@pytest.mark.parametrize("fmt,S,beta", [("bf16", 5, 9), ("int8", 7, 7), ("fp8", 10, 5)])
 def test_split_contraction_longer_than_8192(fmt, S, beta):
     rng = np.random.default_rng(163)
     a = mi.scaled_f64(rng, (200, 12000))
@@ -1234,3 +1234,53 @@ def test_few_rows_all_rows_per_thread(case):
     for op1, op2 in pairs:
         say("few rows", what, op1, op2)
         eq(host(G.inner(ga, gb, op1, op2)), oracle.inner(a, b, op1, op2, mode="native"))
+
+
+
+# ---------------------------------------------------------------------------
+# FP8 (E4M3) slices: 5-bit signed digits, exact FP32 levels folded every
+# 4096 k, so the GPU sums the oracle's scheme exactly (up to FP64 rounding).
+
+@pytest.mark.parametrize("shape", [(100, 300, 70), (64, 64, 128), (1, 1, 1), (257, 1000, 131), (33, 65, 200)])
+def test_split_fp8_matches_oracle_scheme(shape):
+    M, K, N = shape
+    rng = np.random.default_rng(180)
+    a = mi.scaled_f64(rng, (M, K))
+    b = mi.scaled_f64(rng, (K, N))
+    ref = oracle.inner_dot2(a, b)
+    for S in range(1, 11):
+        say("split fp8", shape, "S", S)
+        d = host(G.inner_split(gpu(a), gpu(b), "fp8", S))
+        want = oracle.split_inner(a, b, nslices=S, beta=5)
+        assert nerr(d, want) <= scheme_tol("fp8", S), (S, nerr(d, want))
+        if S >= 10:
+            assert nerr(d, ref) <= 1e-12, (S, nerr(d, ref))
+
+
+def test_split_fp8_exact_integers():
+    # Integers in [-15, 15] whose row/column maximum lies in [8, 16) are one
+    # signed 5-bit digit each: one FP8 slice gives the exact product.
+    rng = np.random.default_rng(181)
+    a = mi.small_int_f64(rng, (90, 700), 15)
+    b = mi.small_int_f64(rng, (700, 70), 15)
+    a[:, 3] = 9.0
+    b[5, :] = -12.0
+    say("split fp8 exact integers")
+    d = host(G.inner_split(gpu(a), gpu(b), "fp8", 1))
+    eq(d, (a.astype(np.int64) @ b.astype(np.int64)).astype(np.float64))
+
+
+def test_split_fp8_full_size_sampled():
+    a, b = mi.workload_split()
+    say("split fp8 8192^3 S=10")
+    d = G.inner_split(gpu(a), gpu(b), "fp8", 10)
+    rows = _sample_rows(np.random.default_rng(10), 8192, 10)
+    got = host(d[torch.from_numpy(rows).to(DEV)])
+    ref = oracle.inner_dot2(a, b, rows=rows)
+    e = nerr(got, ref)
+    scale = oracle.abs_product(a, b, rows=rows)
+    say("split fp8 8192^3 vs Dot2: normwise %.3e, max-norm %.3e, componentwise %.3e"
+        % (e, oracle.maxnorm_error(got, ref), oracle.componentwise_error(got, ref, scale)))
+    assert e <= 1e-12
+    want = oracle.split_inner(a, b, nslices=10, beta=5, rows=rows[:4])
+    assert nerr(got[:4], want) <= 1e-14

@@ -642,3 +642,14 @@ def test_split_s5_beta9_meets_tolerance_on_more_seeds():
         ref = oracle.inner_dot2(a, b)
         errs.append(oracle.normwise_error(oracle.split_inner(a, b, nslices=5, beta=9), ref))
     assert max(errs) <= 1e-12, errs
+
+
+def test_split_fp8_parameters_meet_tolerance_on_workload_distribution():
+    # FP8 E4M3 digits of 5 bits: 10 slices (55 pairs) meet 1e-12 with a wide
+    # margin on the workload distribution at K = 8192; 8 slices do not.
+    rng = mi.rng_for(mi.SPLIT_PRECISION, salt=5)
+    a = mi.scaled_f64(rng, (8, 8192))
+    b = mi.scaled_f64(rng, (8192, 24))
+    ref = oracle.inner_dot2(a, b)
+    assert oracle.normwise_error(oracle.split_inner(a, b, nslices=10, beta=5), ref) <= 1e-13
+    assert oracle.normwise_error(oracle.split_inner(a, b, nslices=8, beta=5), ref) > 1e-12
