@@ -32,6 +32,7 @@
 #include "common.hpp"
 #include "internal.hpp"
 #include "split_gemm.hpp"
+#include "split_gemm_f8.hpp"
 
 namespace moa {
 
