@@ -29,7 +29,9 @@ namespace moa {
 // are never stored).
 // blockIdx.y selects a group of MR rows (a grid with gridDim.y > 1 splits
 // the rows over workgroups: each reads B again, from cache when B is small).
-template <typename T, int OP1, int OP2, int MR, int R>
+// RING: stream B through a per-thread prefetch ring (used for four or more
+// rows per thread on grids of at most four workgroups per CU; see below).
+template <typename T, int OP1, int OP2, int MR, int R, bool RING = false>
 __global__ __launch_bounds__(256) void k_skinny(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
                                                 int M, int64_t K, int64_t N, bool vec_ok) {
   constexpr int VEC = 16 / sizeof(T);
@@ -60,9 +62,56 @@ __global__ __launch_bounds__(256) void k_skinny(const T *__restrict__ A, const T
     }
   };
   using V = T __attribute__((ext_vector_type(VEC)));
-  if (vec_ok && blk0 + SPAN * R <= N) {
-    // Whole block inside the row: 16-byte non-temporal loads, several rows
-    // of B in flight per thread.
+  if (RING && vec_ok && blk0 + SPAN * R <= N) {
+    // Whole block inside the row: 16-byte non-temporal loads through a ring
+    // of PF rows of B per thread. Row l + PF is requested as soon as row l is
+    // folded, so PF - 1 rows stay in flight however few waves the grid gives
+    // each SIMD (the fold itself must stay sequential in l).
+    constexpr int PF = 8;
+    V ring[PF][R];
+    auto fetch = [&](int64_t l, V(&dst)[R]) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r] = __builtin_nontemporal_load((const V *)(B + l * N + j0 + r * SPAN));
+    };
+    auto fold_v = [&](int64_t l, const V(&src)[R]) {
+      T b[R][VEC];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) b[r][v] = src[r][v];
+      fold_row(l, b);
+    };
+    int64_t l0 = 0;
+    if (K >= 2 * PF) {
+      // Branch-free steady state: the ring holds rows l0 .. l0 + PF - 1 and
+      // every row fetched inside the loop exists.
+#pragma unroll
+      for (int p = 0; p < PF; ++p) fetch(p, ring[p]);
+      for (; l0 + 2 * PF <= K; l0 += PF) {
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+          // Fold, then refill the slot: the new row takes the registers of
+          // the row just used (no copy, so no wait for the new load).
+          fold_v(l0 + p, ring[p]);
+          fetch(l0 + PF + p, ring[p]);
+          // Keep each refill where it is (not sunk below later folds).
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < PF; ++p) fold_v(l0 + p, ring[p]);
+      l0 += PF;
+    }
+    // Remaining rows (fewer than PF, or all of a short contraction).
+#pragma unroll 4
+    for (int64_t l = l0; l < K; ++l) {
+      V cur[R];
+      fetch(l, cur);
+      fold_v(l, cur);
+    }
+  } else if (vec_ok && blk0 + SPAN * R <= N) {
+    // Whole block inside the row: 16-byte non-temporal loads, unrolled so
+    // that several rows of B are in flight per thread.
 #pragma unroll 4
     for (int64_t l = 0; l < K; ++l) {
       T b[R][VEC];
@@ -122,8 +171,18 @@ static hipError_t launch_mr(const T *A, const T *B, T *D, int64_t M, int64_t K, 
     hipLaunchKernelGGL((k_skinny<T, OP1, OP2, 1, R>), g, b, 0, s, A, B, D, m, K, N, vec_ok);
   else if (M == 2)
     hipLaunchKernelGGL((k_skinny<T, OP1, OP2, 2, R>), g, b, 0, s, A, B, D, m, K, N, vec_ok);
+  // Four or more rows per thread on a grid of at most four workgroups per CU
+  // (n up to 2^19 FP64 columns with one run per thread, 2^21 with four): the
+  // waves are too few to keep HBM busy with a few rows of B in flight each,
+  // so each thread streams B through its prefetch ring. 4 x 128 . 128 x n
+  // FP64: n = 2^18 0.076 -> 0.047 ms, n = 2^20 0.21 -> 0.17 ms. On larger
+  // grids the ring's registers cost occupancy (n = 2^22: 0.68 -> 0.78 ms).
+  else if (M <= 4 && blocks <= 1024)
+    hipLaunchKernelGGL((k_skinny<T, OP1, OP2, 4, R, true>), g, b, 0, s, A, B, D, m, K, N, vec_ok);
   else if (M <= 4)
     hipLaunchKernelGGL((k_skinny<T, OP1, OP2, 4, R>), g, b, 0, s, A, B, D, m, K, N, vec_ok);
+  else if (M <= 8 && blocks <= 1024)
+    hipLaunchKernelGGL((k_skinny<T, OP1, OP2, 8, R, true>), g, b, 0, s, A, B, D, m, K, N, vec_ok);
   else if (M <= 8)
     hipLaunchKernelGGL((k_skinny<T, OP1, OP2, 8, R>), g, b, 0, s, A, B, D, m, K, N, vec_ok);
   else
