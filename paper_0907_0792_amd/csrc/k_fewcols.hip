@@ -35,11 +35,13 @@ __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const 
   constexpr int VW = 16 / (int)sizeof(T), SPAN = kWave * VW, NSPAN = kChunk / SPAN;
   typedef __attribute__((__vector_size__(16))) T vec_t;
   // Row l of a chunk sits at LDS row (l / SPAN) SPAN + (l % VW) 64 + (l % SPAN) / VW,
-  // so the 64 lanes reading their u-th values of one column read 64 rows in a
-  // row; the row stride is odd (NC + 1 words or double words), so those reads
-  // hit distinct banks.
-  constexpr int SB = NC == 1 ? 1 : NC + 1;
-  __shared__ T Bs[kChunk * SB];
+  // so the 64 lanes reading their u-th values read 64 consecutive rows: with
+  // rows of exactly NC elements that is one contiguous block, read as 16-byte
+  // vectors (a lane takes its row's NC values in NC / VW reads, and
+  // neighbouring lanes read neighbouring 16 bytes).
+  constexpr int SB = NC;
+  constexpr int RV = (NC * (int)sizeof(T) + 15) / 16;  // 16-byte reads per row
+  __shared__ __attribute__((aligned(16))) T Bs[kChunk * SB];
   const int tid = threadIdx.x, lane = tid % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * R;
@@ -105,18 +107,31 @@ __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const 
       const int l0 = h * SPAN + VW * lane;  // this lane's first l in the chunk
       if (kc == kChunk) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          if (c < N) {
-            T b[VW];
+        for (int u = 0; u < VW; u += 2) {  // pairs of terms (three-operand fold for int32)
+          T b[2][RV * VW];
 #pragma unroll
-            for (int u = 0; u < VW; ++u) b[u] = Bs[(h * SPAN + u * kWave + lane) * SB + c];
+          for (int w = 0; w < 2; ++w) {
+            const T *row = &Bs[(h * SPAN + (u + w) * kWave + lane) * SB];
+            if constexpr (NC * sizeof(T) >= 16) {
 #pragma unroll
-            for (int r = 0; r < R; ++r)
+              for (int q = 0; q < RV; ++q) {
+                const vec_t v = *(const vec_t *)(row + q * VW);
 #pragma unroll
-              for (int u = 0; u < VW; u += 2)  // pairs of terms (three-operand fold for int32)
-                acc[r][c] = fold_pair<OP1>(acc[r][c], apply_op<OP2>(x[h][r][u], b[u]),
-                                           apply_op<OP2>(x[h][r][u + 1], b[u + 1]));
+                for (int e = 0; e < VW; ++e) b[w][q * VW + e] = v[e];
+              }
+            } else {
+#pragma unroll
+              for (int c = 0; c < NC; ++c) b[w][c] = row[c];
+            }
           }
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            if (c < N) {
+#pragma unroll
+              for (int r = 0; r < R; ++r)
+                acc[r][c] = fold_pair<OP1>(acc[r][c], apply_op<OP2>(x[h][r][u], b[0][c]),
+                                           apply_op<OP2>(x[h][r][u + 1], b[1][c]));
+            }
         }
       } else {
 #pragma unroll
@@ -154,12 +169,12 @@ __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const 
   }
 }
 
-// Rows per wave (each staged B element feeds R terms): 2, measured on int32
-// (max,+) 65536 x 4096 . 4096 x 8 (0.220 ms; 4 rows: 0.223 ms with twice the
-// registers).
+// Rows per wave (each staged B row, read as 16-byte vectors, feeds R terms
+// per value): 4, measured on int32 (max,+) 65536 x 4096 . 4096 x 8 over ten
+// back-to-back calls (0.234 ms; 2 rows: 0.247 ms).
 template <typename T, int NC>
 constexpr int rows_per_wave() {
-  return 2;
+  return 4;
 }
 
 template <typename T, int OP1, int OP2, int NC>
