@@ -233,15 +233,15 @@ moa_status moa_inner_grad(moa_shape sa, const void *A, moa_shape sb, const void 
  * Batches of uneven (+,*) inner products in one persistent launch.
  *
  * moa_batch_build validates every problem on the host, orders the work by
- * estimated cost, uploads a device descriptor table (problem shapes,
- * pointers, tile choice per problem from the tile table) and work list on
- * `stream`, waits for that upload, and captures the persistent launch in a
+ * estimated cost, uploads the work list (one record per output tile: the
+ * problem's pointers and shape, the tile choice from the tile table and the
+ * tile's origin) on `stream`, waits for that upload, and captures the persistent launch in a
  * HIP graph (on a private stream: capture is not allowed on the default
  * stream). Each D[i] must hold the whole result of problem i (its shape is
  * that of moa_inner_shape(sa[i], sb[i])). The caller's A[i], B[i], D[i] (device
  * pointers, dtype dt = MOA_F32 or MOA_F64) must stay valid while the batch
  * exists; moa_batch_run replays the graph (one kernel launch). A batch owns
- * only its descriptor table, work list and graph; moa_batch_free releases
+ * only its work list and graph; moa_batch_free releases
  * them. A run keeps no state, but concurrent runs of one batch write the
  * same D arrays.
  */

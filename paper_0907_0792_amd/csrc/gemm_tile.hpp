@@ -29,6 +29,12 @@ struct Mfma16<float> {
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane / 16) + v; }
 };
 
+// LDS bytes of one tile's panels (A: BK x (BM + 2), B: BK x (BN + 2)).
+template <typename T, int WBM, int WBN, int BK>
+constexpr int gemm_tile_lds_bytes() {
+  return (int)sizeof(T) * BK * (32 * WBM + 2 + 32 * WBN + 2);
+}
+
 // One BM x BN tile of D = A . B (BM = 32*WBM, BN = 32*WBN), computed by the
 // 256 threads of a workgroup with BK-wide k panels. m0, n0: tile origin.
 // GEN: A and B are the strided (P, K, Q) views of a contraction over any
@@ -49,10 +55,14 @@ struct Mfma16<float> {
 // I: index type. int32_t when the caller knows every offset of the tile
 // (operand and result extents padded by a tile) fits in 31 bits: 32-bit
 // address arithmetic takes fewer registers (small batched problems).
+// smem: the panels' LDS (at least gemm_tile_lds_bytes, 16-byte aligned),
+// given by the caller so that a kernel running tiles of several shapes holds
+// one buffer sized for the largest instead of one per shape; gemm_tile below
+// declares its own.
 template <typename T, bool TA, bool TB, int WBM, int WBN, int BK = 16, bool GEN = false, bool SKIP = false,
           bool VEC = false, typename I = int64_t>
-__device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
-                                          I M, I K, I N, I m0, I n0, I Qa = 1, I Qb = 1) {
+__device__ __forceinline__ void gemm_tile_at(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
+                                             I M, I K, I N, I m0, I n0, I Qa, I Qb, unsigned char *smem) {
   using MF = Mfma16<T>;
   using acc_t = typename MF::acc_t;
   constexpr int BM = 32 * WBM, BN = 32 * WBN;
@@ -60,8 +70,8 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
   constexpr int V = VEC ? 16 / (int)sizeof(T) : 1;  // elements per load
   typedef __attribute__((__vector_size__(V * sizeof(T)))) T vec_t;
-  __shared__ T As[BK][BM + PAD];
-  __shared__ T Bs[BK][BN + PAD];
+  T(*As)[BM + PAD] = reinterpret_cast<T(*)[BM + PAD]>(smem);
+  T(*Bs)[BN + PAD] = reinterpret_cast<T(*)[BN + PAD]>(smem + sizeof(T) * BK * (BM + PAD));
 
   const int tid = threadIdx.x, lane = tid % kWave, wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const int wm = wave / 2, wn = wave % 2;
@@ -181,13 +191,7 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
     }
   };
 
-  const I nk = (K + BK - 1) / BK;
-  if (nk > 0) load(0);
-  for (I kt = 0; kt < nk; ++kt) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (kt + 1 < nk) load((kt + 1) * BK);
+  auto compute = [&]() {
 #pragma unroll
     for (int k4 = 0; k4 < BK; k4 += 4) {
       T a[WBM], b[WBN];
@@ -201,6 +205,17 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
         for (int j = 0; j < WBN; ++j)
           if (!SKIP || (i < nbm && j < nbn)) acc[i][j] = MF::run(a[i], b[j], acc[i][j]);
     }
+  };
+
+  // The next panel is fetched into registers while this one is multiplied.
+  const I nk = (K + BK - 1) / BK;
+  if (nk > 0) load(0);
+  for (I kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (kt + 1 < nk) load((kt + 1) * BK);
+    compute();
   }
   __syncthreads();  // LDS is reused by the caller's next tile
 #pragma unroll
@@ -213,6 +228,14 @@ __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__re
         const I gn = n0 + wn * (BN / 2) + j * 16 + lane % 16;
         if (gm < M && gn < N) D[gm * N + gn] = acc[i][j][v];
       }
+}
+
+template <typename T, bool TA, bool TB, int WBM, int WBN, int BK = 16, bool GEN = false, bool SKIP = false,
+          bool VEC = false, typename I = int64_t>
+__device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
+                                          I M, I K, I N, I m0, I n0, I Qa = 1, I Qb = 1) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_tile_lds_bytes<T, WBM, WBN, BK>()];
+  gemm_tile_at<T, TA, TB, WBM, WBN, BK, GEN, SKIP, VEC, I>(A, B, D, M, K, N, m0, n0, Qa, Qb, smem);
 }
 
 }  // namespace moa

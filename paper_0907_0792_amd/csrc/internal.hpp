@@ -71,18 +71,23 @@ hipError_t launch_split_prepare(const SplitPlan &p, const double *A, const doubl
 hipError_t launch_split_multiply(const SplitPlan &p, double *D, void *ws, hipStream_t s);
 
 // Batched persistent (+,*) products.
-struct BatchDesc {
+struct BatchDesc {  // one problem (host side, while the work list is built)
   const void *A;
   const void *B;
   void *D;
   int32_t M, K, N;
-  int32_t tile;       // tile variant
-  int32_t tiles_n;    // tiles along N for this problem
-  int32_t first_item; // index of this problem's first work item
+  int32_t tile;     // tile variant
+  int32_t tiles_n;  // tiles along N for this problem
 };
+// One work item: one output tile of one problem, self-contained (the
+// kernel reads one record per item, with no second, dependent load).
 struct BatchItem {
-  int32_t prob;
-  int32_t tile;  // tile index within the problem
+  const void *A;
+  const void *B;
+  void *D;
+  int32_t M, K, N;
+  int32_t tile;    // tile variant
+  int32_t m0, n0;  // tile origin
 };
 
 }  // namespace moa

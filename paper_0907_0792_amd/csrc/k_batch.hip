@@ -2,11 +2,11 @@
 //
 // Each problem i is the (+,*) case of Eq. inner (Section I) on its own
 // flattened M_i x K_i . K_i x N_i view. The batch is cut into work items
-// (one output tile of one problem each) ordered by estimated cost, largest
-// first, and a persistent grid (as many workgroups as fit on the GPU at once)
-// takes them round-robin, so each workgroup gets a similar mix of large and
-// small items. The launch has no state between replays, so the captured graph
-// replays as is.
+// (one output tile of one problem each), and a persistent grid (as many
+// workgroups as fit on the GPU at once) runs them: at build time the items
+// are dealt to the workgroups by the longest-processing-time rule on an
+// estimated cost, so the workgroups finish close together. The launch has no
+// state between replays, so the captured graph replays as is.
 //
 // Tile variants (per problem, from the tile table):
 //   0: 32 x 32 tiles (one 16 x 16 MFMA block per wave)
@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <mutex>
 #include <numeric>
+#include <queue>
 #include <random>
 #include <string>
 #include <vector>
@@ -36,8 +37,8 @@ struct moa_batch {
   moa_dtype dt;
   int32_t n;
   int64_t items;
-  moa::BatchDesc *d_desc;
   moa::BatchItem *d_items;
+  int64_t *d_first;  // grid + 1 offsets: workgroup g runs items [d_first[g], d_first[g + 1])
   hipGraph_t graph;
   hipGraphExec_t exec;
   int grid;
@@ -65,31 +66,34 @@ int g_table[kBuckets] = {1, 1, 1, 1, 1, 1, 1, 1};
 // problem, padded by a tile, fits in 31 bits: fewer registers, one more
 // workgroup per CU; 0.284 -> 0.265 ms on the 10,000-problem workload).
 template <typename T, typename I>
-__global__ __launch_bounds__(256, 2) void k_batch(const BatchDesc *__restrict__ desc,
-                                                   const BatchItem *__restrict__ items, int64_t n_items) {
-  // Items are taken round-robin (costliest first): one shared counter for
-  // every item serialises ~n_items atomics on one address, which measured as
-  // ~15 us of fixed cost per item per workgroup.
-  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const BatchItem w = items[it];
-    const BatchDesc p = desc[w.prob];
-    const I side = (p.tile == 0) ? 32 : 64;
-    const I tm = w.tile / p.tiles_n, tn = w.tile % p.tiles_n;
+__global__ __launch_bounds__(256, 2) void k_batch(const BatchItem *__restrict__ items,
+                                                   const int64_t *__restrict__ first) {
+  // Workgroup g runs items first[g] .. first[g + 1] - 1 (its share, fixed at
+  // build time). The next item's record is requested before this item's tile
+  // starts, so its latency is hidden. One LDS buffer, sized for the larger
+  // tile, serves both.
+  __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_tile_lds_bytes<T, 2, 2, 16>()];
+  int64_t it = first[blockIdx.x];
+  const int64_t end = first[blockIdx.x + 1];
+  if (it >= end) return;
+  BatchItem w = items[it];
+  for (; it < end; ++it) {
+    const BatchItem wn = items[it + 1 < end ? it + 1 : it];  // uniform: a scalar load
+    const T *a = (const T *)w.A, *b = (const T *)w.B;
+    T *d = (T *)w.D;
     // SKIP: blocks past the problem's edge issue no MFMA, so the matrix-core
     // work follows M and N in steps of 16 rather than the tile side.
-    if (p.tile == 0)
-      gemm_tile<T, false, false, 1, 1, 16, false, true, false, I>((const T *)p.A, (const T *)p.B, (T *)p.D, p.M, p.K,
-                                                                  p.N, tm * side, tn * side);
+    if (w.tile == 0)
+      gemm_tile_at<T, false, false, 1, 1, 16, false, true, false, I>(a, b, d, w.M, w.K, w.N, w.m0, w.n0, 1, 1, smem);
     else
-      gemm_tile<T, false, false, 2, 2, 16, false, true, false, I>((const T *)p.A, (const T *)p.B, (T *)p.D, p.M, p.K,
-                                                                  p.N, tm * side, tn * side);
+      gemm_tile_at<T, false, false, 2, 2, 16, false, true, false, I>(a, b, d, w.M, w.K, w.N, w.m0, w.n0, 1, 1, smem);
+    w = wn;
   }
 }
 
-
-// As many workgroups as can be resident at once (CUs x occupancy): with
-// round-robin items, a workgroup that had to wait for a free slot would run
-// its share after everyone else.
+// As many workgroups as can be resident at once (CUs x occupancy): every
+// workgroup's share is fixed at build time, and one that had to wait for a
+// free slot would run its share after everyone else.
 template <typename T, typename I>
 int persistent_grid() {
   int dev = 0, cus = 256, per_cu = 4;
@@ -113,8 +117,8 @@ void free_batch(moa_batch *b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  if (b->d_desc) (void)hipFree(b->d_desc);
   if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_first) (void)hipFree(b->d_first);
   delete b;
 }
 
@@ -134,7 +138,6 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
   if (n > 0 && (!sa || !sb || !A || !B || !D)) return set_error(MOA_ERR_NULL, "batch array is NULL");
   const size_t es = dt == MOA_F64 ? 8 : 4;
   std::vector<BatchDesc> desc((size_t)n);
-  std::vector<int64_t> cost((size_t)n);
   int table[kBuckets];
   {
     std::lock_guard<std::mutex> lk(g_table_mu);
@@ -169,27 +172,60 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
     d.N = (int32_t)N;
     d.tile = v;
     d.tiles_n = (int32_t)((N + side - 1) / side);
-    d.first_item = (int32_t)total_items;
     const int64_t tiles = ((M + side - 1) / side) * d.tiles_n;
     total_items += (M * N > 0) ? tiles : 0;
-    cost[(size_t)i] = (int64_t)side * side * (K > 0 ? K : 1);
   }
-  // Work items, costliest first (longest-processing-time order).
-  std::vector<BatchItem> items;
-  items.reserve((size_t)total_items);
-  std::vector<int32_t> order((size_t)n);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[(size_t)x] > cost[(size_t)y]; });
-  for (int32_t i : order) {
+  // Work items, one per output tile. A tile of these small problems is bound
+  // by load latency: its time is about a fixed cost plus one round trip per
+  // 16-wide k panel, whatever the tile side, so its cost is 2 + ceil(K / 16)
+  // panel times. The items are dealt to the persistent workgroups by the
+  // longest-processing-time rule (costliest first, each to the workgroup
+  // with the least work so far; ties to the lowest index), and each
+  // workgroup's items are stored contiguously.
+  const int grid = dt == MOA_F32 ? (idx32 ? persistent_grid<float, int32_t>() : persistent_grid<float, int64_t>())
+                                 : (idx32 ? persistent_grid<double, int32_t>() : persistent_grid<double, int64_t>());
+  struct Tile {
+    int32_t prob, t;
+    int64_t cost;
+  };
+  std::vector<Tile> tiles_all;
+  tiles_all.reserve((size_t)total_items);
+  for (int32_t i = 0; i < n; ++i) {
     const BatchDesc &d = desc[(size_t)i];
     if ((int64_t)d.M * d.N == 0) continue;
     const int side = kTileSide[d.tile];
     const int64_t tiles = ((d.M + side - 1) / side) * (int64_t)d.tiles_n;
-    for (int64_t t = 0; t < tiles; ++t) items.push_back(BatchItem{i, (int32_t)t});
+    for (int64_t t = 0; t < tiles; ++t) tiles_all.push_back(Tile{i, (int32_t)t, 2 + ((int64_t)d.K + 15) / 16});
   }
-  // Zero-K problems: result is the empty sum, filled at build time below by
-  // the identity kernel inside the graph is not needed; handled as items with
-  // K = 0 (the tile loop writes zeros).
+  std::stable_sort(tiles_all.begin(), tiles_all.end(), [](const Tile &x, const Tile &y) { return x.cost > y.cost; });
+  std::vector<int32_t> owner(tiles_all.size());
+  std::vector<int64_t> count((size_t)grid, 0);
+  {
+    typedef std::pair<int64_t, int32_t> Slot;  // (work so far, workgroup)
+    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+    for (int32_t g = 0; g < grid; ++g) heap.push(Slot{0, g});
+    for (size_t k = 0; k < tiles_all.size(); ++k) {
+      Slot sl = heap.top();
+      heap.pop();
+      owner[k] = sl.second;
+      ++count[(size_t)sl.second];
+      sl.first += tiles_all[k].cost;
+      heap.push(sl);
+    }
+  }
+  std::vector<int64_t> first((size_t)grid + 1, 0);
+  for (int32_t g = 0; g < grid; ++g) first[(size_t)g + 1] = first[(size_t)g] + count[(size_t)g];
+  std::vector<BatchItem> items(tiles_all.size());
+  {
+    std::vector<int64_t> next(first.begin(), first.end() - 1);
+    for (size_t k = 0; k < tiles_all.size(); ++k) {
+      const BatchDesc &d = desc[(size_t)tiles_all[k].prob];
+      const int side = kTileSide[d.tile];
+      const int32_t t = tiles_all[k].t;
+      items[(size_t)next[(size_t)owner[k]]++] =
+          BatchItem{d.A, d.B, d.D, d.M, d.K, d.N, d.tile, t / d.tiles_n * side, t % d.tiles_n * side};
+    }
+  }
 
   moa_batch *b = new moa_batch();
   memset(b, 0, sizeof *b);
@@ -197,21 +233,19 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
   b->n = n;
   b->items = (int64_t)items.size();
   b->idx32 = idx32;
-  if (dt == MOA_F32)
-    b->grid = idx32 ? persistent_grid<float, int32_t>() : persistent_grid<float, int64_t>();
-  else
-    b->grid = idx32 ? persistent_grid<double, int32_t>() : persistent_grid<double, int64_t>();
+  b->grid = grid;
   hipError_t e;
   hipStream_t cap = nullptr;
-  if (n > 0 && (e = hipMalloc(&b->d_desc, sizeof(BatchDesc) * (size_t)n)) != hipSuccess) goto hip_error;
   if (!items.empty() && (e = hipMalloc(&b->d_items, sizeof(BatchItem) * items.size())) != hipSuccess) goto hip_error;
-  // The tables are uploaded on `stream` (ordered after the caller's earlier
-  // work there) and build waits for the copies, so the host vectors may go.
-  if (n > 0 && (e = hipMemcpyAsync(b->d_desc, desc.data(), sizeof(BatchDesc) * (size_t)n, hipMemcpyHostToDevice,
-                                   (hipStream_t)stream)) != hipSuccess)
-    goto hip_error;
+  if ((e = hipMalloc(&b->d_first, sizeof(int64_t) * first.size())) != hipSuccess) goto hip_error;
+  // The work list and the shares are uploaded on `stream` (ordered after the
+  // caller's earlier work there) and build waits for the copies, so the host
+  // vectors may go.
   if (!items.empty() && (e = hipMemcpyAsync(b->d_items, items.data(), sizeof(BatchItem) * items.size(),
                                             hipMemcpyHostToDevice, (hipStream_t)stream)) != hipSuccess)
+    goto hip_error;
+  if ((e = hipMemcpyAsync(b->d_first, first.data(), sizeof(int64_t) * first.size(), hipMemcpyHostToDevice,
+                          (hipStream_t)stream)) != hipSuccess)
     goto hip_error;
   if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) goto hip_error;
   // Capture the persistent launch on a private stream (capture is not allowed
@@ -221,13 +255,13 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
   if (b->items > 0) {
     const dim3 g((unsigned)b->grid), t(256);
     if (dt == MOA_F32 && idx32)
-      hipLaunchKernelGGL((k_batch<float, int32_t>), g, t, 0, cap, b->d_desc, b->d_items, b->items);
+      hipLaunchKernelGGL((k_batch<float, int32_t>), g, t, 0, cap, b->d_items, b->d_first);
     else if (dt == MOA_F32)
-      hipLaunchKernelGGL((k_batch<float, int64_t>), g, t, 0, cap, b->d_desc, b->d_items, b->items);
+      hipLaunchKernelGGL((k_batch<float, int64_t>), g, t, 0, cap, b->d_items, b->d_first);
     else if (idx32)
-      hipLaunchKernelGGL((k_batch<double, int32_t>), g, t, 0, cap, b->d_desc, b->d_items, b->items);
+      hipLaunchKernelGGL((k_batch<double, int32_t>), g, t, 0, cap, b->d_items, b->d_first);
     else
-      hipLaunchKernelGGL((k_batch<double, int64_t>), g, t, 0, cap, b->d_desc, b->d_items, b->items);
+      hipLaunchKernelGGL((k_batch<double, int64_t>), g, t, 0, cap, b->d_items, b->d_first);
   }
   if ((e = hipStreamEndCapture(cap, &b->graph)) != hipSuccess) goto hip_error;
   if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) goto hip_error;

@@ -712,7 +712,26 @@ def test_batch_small_full_check():
     bt.close()
 
 
-def test_batch_wide_problem_64bit_offsets():
+BATCH_VARIANTS = (0, 1)
+
+
+class _tile_variant:
+    """Every bucket of the batch tile table set to one variant, restored on exit."""
+
+    def __init__(self, v):
+        self.v = v
+
+    def __enter__(self):
+        self.saved = moa.tile_table()
+        moa.set_tile_table("\n".join(" ".join(l.split()[:3] + [str(self.v)])
+                                     for l in self.saved.strip().splitlines()))
+
+    def __exit__(self, *exc):
+        moa.set_tile_table(self.saved)
+
+
+@pytest.mark.parametrize("variant", BATCH_VARIANTS)
+def test_batch_wide_problem_64bit_offsets(variant):
     # A problem whose padded extents pass 2^31 offsets makes the whole batch
     # use 64-bit tile index arithmetic. Small integer entries: exact sums.
     rng = np.random.default_rng(115)
@@ -722,8 +741,9 @@ def test_batch_wide_problem_64bit_offsets():
     As, Bs = [gpu(a) for a in a_s], [gpu(b) for b in b_s]
     pool = GuardPool([((sa[0], sb[1]), torch.float32) for sa, sb in shapes])
     Ds = pool.t
-    say("batch with a 2 x 3 . 3 x 32.1M problem")
-    bt = moa.Batch(As, Bs, Ds)
+    say("batch with a 2 x 3 . 3 x 32.1M problem, tile variant", variant)
+    with _tile_variant(variant):
+        bt = moa.Batch(As, Bs, Ds)
     bt.run()
     pool.check("batch with 64-bit offsets")
     for a, b, d in zip(a_s, b_s, Ds):
@@ -908,7 +928,8 @@ def test_split_two_stage_api_matches_one_call():
         eq(host(out), one)
 
 
-def test_batch_fp64():
+@pytest.mark.parametrize("variant", BATCH_VARIANTS)
+def test_batch_fp64(variant):
     rng = np.random.default_rng(121)
     shapes = mi.batch_shapes(rng, 300)
     probs = [(sa, sb, mi.uniform_f64(rng, sa), mi.uniform_f64(rng, sb)) for sa, sb in shapes]
@@ -916,8 +937,9 @@ def test_batch_fp64():
     Bs = [gpu(b) for _, _, _, b in probs]
     pool = GuardPool([(moa.inner_shape(sa, sb), torch.float64) for sa, sb, _, _ in probs])
     Ds = pool.t
-    say("batch fp64 300")
-    bt = moa.Batch(As, Bs, Ds)
+    say("batch fp64 300, tile variant", variant)
+    with _tile_variant(variant):
+        bt = moa.Batch(As, Bs, Ds)
     bt.run()
     pool.check("batch fp64")
     for (sa, sb, a, b), d in zip(probs, Ds):
@@ -1064,28 +1086,23 @@ def test_fp32_grad_exact_integers(M, K, N):
 
 
 def test_fp32_batch_exact_integers_32bit_index():
-    # The production batch kernel (32-bit tile offsets, both tile variants via
+    # The production batch kernel (32-bit tile offsets, every tile variant via
     # the table) on the batch workload's shape distribution, every problem
     # compared element by element.
     rng = np.random.default_rng(162)
     shapes = mi.batch_shapes(rng, 800)
     a_s = [_ints32(rng, sa) for sa, _ in shapes]
     b_s = [_ints32(rng, sb) for _, sb in shapes]
-    saved = moa.tile_table()
-    try:
-        for variant in (0, 1):
-            table = "\n".join(" ".join(l.split()[:3] + [str(variant)]) for l in saved.strip().splitlines())
-            moa.set_tile_table(table)
-            pool = GuardPool([(moa.inner_shape(sa, sb), torch.float32) for sa, sb in shapes])
-            say("batch exact, tile variant", variant)
+    for variant in BATCH_VARIANTS:
+        pool = GuardPool([(moa.inner_shape(sa, sb), torch.float32) for sa, sb in shapes])
+        say("batch exact, tile variant", variant)
+        with _tile_variant(variant):
             bt = moa.Batch([gpu(a) for a in a_s], [gpu(b) for b in b_s], pool.t)
-            bt.run()
-            pool.check("exact batch, variant %d" % variant)
-            for a, b, d in zip(a_s, b_s, pool.t):
-                eq(host(d), _exact_tensordot(a, a.ndim - 1, b, 0))
-            bt.close()
-    finally:
-        moa.set_tile_table(saved)
+        bt.run()
+        pool.check("exact batch, variant %d" % variant)
+        for a, b, d in zip(a_s, b_s, pool.t):
+            eq(host(d), _exact_tensordot(a, a.ndim - 1, b, 0))
+        bt.close()
 
 
 # ---------------------------------------------------------------------------
