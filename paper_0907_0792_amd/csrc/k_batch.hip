@@ -43,6 +43,7 @@ struct moa_batch {
   hipGraphExec_t exec;
   int grid;
   bool idx32;  // every tile offset fits in 31 bits: 32-bit index arithmetic
+  int kind;    // kernel: 0 LDS-fed FP32, 1 FP32 64-bit index, 2-3 FP64 (32/64-bit index)
 };
 
 namespace moa {
@@ -62,9 +63,10 @@ std::mutex g_table_mu;
 // tile wins on the 10,000-problem mixed workload: 0.281 vs 0.430 ms for 32).
 int g_table[kBuckets] = {1, 1, 1, 1, 1, 1, 1, 1};
 
-// I: index type of the tile arithmetic (int32_t when every offset of every
-// problem, padded by a tile, fits in 31 bits: fewer registers, one more
-// workgroup per CU; 0.284 -> 0.265 ms on the 10,000-problem workload).
+// Register-staged tiles (FP64 batches, and FP32 batches whose offsets do not
+// fit the LDS-fed tile below). I: index type of the tile arithmetic (int32_t
+// when every offset of every problem, padded by a tile, fits in 31 bits:
+// fewer registers, one more workgroup per CU).
 template <typename T, typename I>
 __global__ __launch_bounds__(256, 2) void k_batch(const BatchItem *__restrict__ items,
                                                    const int64_t *__restrict__ first) {
@@ -91,11 +93,154 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchItem *__restrict__ 
   }
 }
 
+// FP32 tiles fed by buffer loads straight into LDS (32-bit offsets: used
+// when every problem's A and B stay below 2^31 bytes and every tile offset
+// fits in 31 bits). Nothing is staged through registers, so NS - 1 k panels
+// of 16 are in flight per workgroup at no register cost; one barrier per
+// panel. Elements past M, N or K get an offset past the buffer's size, and
+// the buffer range check returns zero for them.
+// A panel (rows of 16 k, 64 bytes each): load (ib, rg) has lane l fetch
+// A[16 ib + 4 rg + l / 16][l % 16], four rows of 64 bytes (four cache
+// lines, as a row-major read), into an LDS block of 64 words padded to 68.
+// The v_mfma_f32_16x16x4_f32 fragment of k step ks wants
+// A[16 ib + i][4 ks + c] in lane i + 16 c; it sits in block (ib, i / 4) at
+// word (i % 4) 16 + 4 ks + c, and with the padding the 64 lanes' words fall
+// in 64 different banks.
+// B panel: load (jb, ks) has lane l fetch B[4 ks + l / 16][16 jb + l % 16],
+// which is exactly the fragment's lane order (four rows of 64 bytes).
+// Three panels: six workgroups per CU (LDS-bound), two panels in flight
+// each. On the 10,000-problem FP32 workload, same box: 0.2256 ms against
+// 0.2343 with four panels (four workgroups per CU) and 0.243-0.246 ms for the
+// register-staged tile; loading A fragment-ordered by 4-byte lanes (each
+// load touching 16 rows) instead measured 0.281-0.287 ms.
+constexpr int kLdsStages = 3;
+constexpr int kLdsBlock = 68;  // words per A load block (64 + 4 of padding)
+
+// s_waitcnt immediate that waits until at most n vector-memory operations
+// are outstanding (n < 64) and leaves the other counters alone.
+constexpr int vmcnt_lds(int n) { return 0x0F70 | (n & 15) | ((n >> 4) << 14); }
+
+template <int WB, int NS>
+__device__ __forceinline__ void batch_tile_lds(const BatchItem &w, float *lds) {
+  constexpr int NB = 2 * WB;                          // 16-wide blocks per tile side
+  constexpr int ASZ = 4 * 4 * kLdsBlock;              // A words per stage (sized for WB = 2)
+  constexpr int STAGE = ASZ + 4 * 4 * 64;             // then B
+  constexpr uint32_t kOut = 0x80000000u;              // an offset past every buffer
+  using MF = Mfma16<float>;
+  const int lane = threadIdx.x % kWave, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wm = wave / 2, wn = wave % 2;
+  const int M = w.M, K = w.K, N = w.N, m0 = w.m0, n0 = w.n0;
+  const __amdgpu_buffer_rsrc_t ra =
+      __builtin_amdgcn_make_buffer_rsrc((void *)w.A, (short)0, (int)((uint32_t)M * (uint32_t)K * 4u), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rb =
+      __builtin_amdgcn_make_buffer_rsrc((void *)w.B, (short)0, (int)((uint32_t)K * (uint32_t)N * 4u), 0x00020000);
+  // This wave's loads: A blocks q = wave NB + p = (ib, rg) = (q / 4, q % 4)
+  // and B blocks q = (jb, ks) = (q / 4, q % 4), p < NB.
+  uint32_t abase[NB], bbase[NB];
+  int bkk[NB];
+  bool arow[NB], bcol[NB];
+  const int acol = lane % 16;
+#pragma unroll
+  for (int p = 0; p < NB; ++p) {
+    const int q = wave * NB + p;
+    const int row = m0 + 16 * (q / 4) + 4 * (q % 4) + lane / 16;
+    const int col = n0 + 16 * (q / 4) + lane % 16;
+    bkk[p] = 4 * (q % 4) + lane / 16;
+    arow[p] = row < M;
+    bcol[p] = col < N;
+    abase[p] = (uint32_t)row * (uint32_t)K + (uint32_t)acol;
+    bbase[p] = (uint32_t)bkk[p] * (uint32_t)N + (uint32_t)col;
+  }
+  auto issue = [&](int buf, int k0) {
+    typedef __attribute__((address_space(3))) void *lds_ptr;
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+      const int q = wave * NB + p;
+      const uint32_t oa = (arow[p] && k0 + acol < K) ? (abase[p] + (uint32_t)k0) * 4u : kOut;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)(lds + buf * STAGE + q * kLdsBlock), 4, oa, 0, 0, 0);
+      const uint32_t ob = (bcol[p] && k0 + bkk[p] < K) ? (bbase[p] + (uint32_t)k0 * (uint32_t)N) * 4u : kOut;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr)(lds + buf * STAGE + ASZ + q * 64), 4, ob, 0, 0, 0);
+    }
+  };
+  // Blocks of this wave inside the problem: no MFMA for the others.
+  const int rm = M - (m0 + wm * 16 * WB), rn = N - (n0 + wn * 16 * WB);
+  const int nbm = rm <= 0 ? 0 : (rm >= 16 * WB ? WB : (rm + 15) / 16);
+  const int nbn = rn <= 0 ? 0 : (rn >= 16 * WB ? WB : (rn + 15) / 16);
+  floatx4 acc[WB][WB];
+#pragma unroll
+  for (int i = 0; i < WB; ++i)
+#pragma unroll
+    for (int j = 0; j < WB; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // Fragment word offsets of this lane inside a stage.
+  const int ai = lane % 16, ac = lane / 16;
+  const int afrag = (ai / 4) * kLdsBlock + (ai % 4) * 16 + ac;
+
+  const int nk = (K + 15) / 16;
+#pragma unroll
+  for (int st = 0; st < NS - 1; ++st)
+    if (st < nk) issue(st, 16 * st);
+  for (int kt = 0; kt < nk; ++kt) {
+    // This wave's loads of panel kt are done once at most the later panels'
+    // loads (2 NB each) are outstanding; the barrier then makes every wave's
+    // part visible and frees the buffer of panel kt - 1.
+    if (kt + NS - 2 < nk)
+      __builtin_amdgcn_s_waitcnt(vmcnt_lds(2 * NB * (NS - 2)));
+    else
+      __builtin_amdgcn_s_waitcnt(vmcnt_lds(0));
+    __builtin_amdgcn_s_barrier();
+    if (kt + NS - 1 < nk) issue((kt + NS - 1) % NS, 16 * (kt + NS - 1));
+    const float *stage = lds + (kt % NS) * STAGE;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      float a[WB], b[WB];
+#pragma unroll
+      for (int i = 0; i < WB; ++i) a[i] = stage[(wm * WB + i) * 4 * kLdsBlock + afrag + 4 * ks];
+#pragma unroll
+      for (int j = 0; j < WB; ++j) b[j] = stage[ASZ + ((wn * WB + j) * 4 + ks) * 64 + lane];
+#pragma unroll
+      for (int i = 0; i < WB; ++i)
+#pragma unroll
+        for (int j = 0; j < WB; ++j)
+          if (i < nbm && j < nbn) acc[i][j] = MF::run(a[i], b[j], acc[i][j]);
+    }
+  }
+  // Every wave is done with the panels before the next item's loads reuse them.
+  __builtin_amdgcn_s_barrier();
+#pragma unroll
+  for (int i = 0; i < WB; ++i)
+#pragma unroll
+    for (int j = 0; j < WB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + (wm * WB + i) * 16 + MF::row(lane, v);
+        const int gn = n0 + (wn * WB + j) * 16 + lane % 16;
+        if (gm < M && gn < N) ((float *)w.D)[(int64_t)gm * N + gn] = acc[i][j][v];
+      }
+}
+
+template <int NS>
+__global__ __launch_bounds__(256, 2) void k_batch_lds(const BatchItem *__restrict__ items,
+                                                       const int64_t *__restrict__ first) {
+  __shared__ __attribute__((aligned(16))) float lds[NS * (4 * 4 * kLdsBlock + 4 * 4 * 64)];
+  int64_t it = first[blockIdx.x];
+  const int64_t end = first[blockIdx.x + 1];
+  if (it >= end) return;
+  BatchItem w = items[it];
+  for (; it < end; ++it) {
+    const BatchItem wn = items[it + 1 < end ? it + 1 : it];  // uniform: a scalar load
+    if (w.tile == 0)
+      batch_tile_lds<1, NS>(w, lds);
+    else
+      batch_tile_lds<2, NS>(w, lds);
+    w = wn;
+  }
+}
+
 // As many workgroups as can be resident at once (CUs x occupancy): every
 // workgroup's share is fixed at build time, and one that had to wait for a
 // free slot would run its share after everyone else.
-template <typename T, typename I>
-int persistent_grid() {
+template <typename F>
+int persistent_grid(F kernel) {
   int dev = 0, cus = 256, per_cu = 4;
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
@@ -103,7 +248,7 @@ int persistent_grid() {
       cus = prop.multiProcessorCount;
   }
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch<T, I>, 256, 0) == hipSuccess && occ > 0) per_cu = occ;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 256, 0) == hipSuccess && occ > 0) per_cu = occ;
   return cus * per_cu;
 }
 
@@ -144,7 +289,7 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
     memcpy(table, g_table, sizeof table);
   }
   int64_t total_items = 0;
-  bool idx32 = true;
+  bool idx32 = true, lds_ok = true;
   for (int32_t i = 0; i < n; ++i) {
     int64_t M, K, N;
     moa_status st = validate_inner(sa[i], sb[i], &M, &K, &N);
@@ -153,6 +298,9 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
     // Offsets of a tile reach (extent + tile) x (extent + tile) at most.
     const int64_t lim = (int64_t)1 << 31;
     if ((M + 64) * (K + 64) >= lim || (K + 64) * (N + 64) >= lim || (M + 64) * (N + 64) >= lim) idx32 = false;
+    // Buffer loads address A and B by 32-bit byte offsets, with 2^31 as the
+    // out-of-range marker.
+    if (M * K * (int64_t)es >= lim || K * N * (int64_t)es >= lim) lds_ok = false;
     if (M * K > 0 && !A[i]) return set_error(MOA_ERR_NULL, "A[i] is NULL");
     if (K * N > 0 && !B[i]) return set_error(MOA_ERR_NULL, "B[i] is NULL");
     if (M * N > 0 && !D[i]) return set_error(MOA_ERR_NULL, "D[i] is NULL");
@@ -182,8 +330,14 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
   // longest-processing-time rule (costliest first, each to the workgroup
   // with the least work so far; ties to the lowest index), and each
   // workgroup's items are stored contiguously.
-  const int grid = dt == MOA_F32 ? (idx32 ? persistent_grid<float, int32_t>() : persistent_grid<float, int64_t>())
-                                 : (idx32 ? persistent_grid<double, int32_t>() : persistent_grid<double, int64_t>());
+  // FP32 with 32-bit offsets everywhere: the LDS-fed tile; other FP32
+  // batches the register-staged tile with 64-bit index arithmetic; FP64 the
+  // register-staged tile with 32- or 64-bit index arithmetic.
+  const int kind = dt == MOA_F32 ? (idx32 && lds_ok ? 0 : 1) : (idx32 ? 2 : 3);
+  const int grid = kind == 0   ? persistent_grid(k_batch_lds<kLdsStages>)
+                   : kind == 1 ? persistent_grid(k_batch<float, int64_t>)
+                   : kind == 2 ? persistent_grid(k_batch<double, int32_t>)
+                               : persistent_grid(k_batch<double, int64_t>);
   struct Tile {
     int32_t prob, t;
     int64_t cost;
@@ -233,6 +387,7 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
   b->n = n;
   b->items = (int64_t)items.size();
   b->idx32 = idx32;
+  b->kind = kind;
   b->grid = grid;
   hipError_t e;
   hipStream_t cap = nullptr;
@@ -254,14 +409,12 @@ moa_status moa_batch_build(int32_t n, const moa_shape *sa, const void *const *A,
   if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) goto hip_error;
   if (b->items > 0) {
     const dim3 g((unsigned)b->grid), t(256);
-    if (dt == MOA_F32 && idx32)
-      hipLaunchKernelGGL((k_batch<float, int32_t>), g, t, 0, cap, b->d_items, b->d_first);
-    else if (dt == MOA_F32)
-      hipLaunchKernelGGL((k_batch<float, int64_t>), g, t, 0, cap, b->d_items, b->d_first);
-    else if (idx32)
-      hipLaunchKernelGGL((k_batch<double, int32_t>), g, t, 0, cap, b->d_items, b->d_first);
-    else
-      hipLaunchKernelGGL((k_batch<double, int64_t>), g, t, 0, cap, b->d_items, b->d_first);
+    switch (kind) {
+      case 0: hipLaunchKernelGGL((k_batch_lds<kLdsStages>), g, t, 0, cap, b->d_items, b->d_first); break;
+      case 1: hipLaunchKernelGGL((k_batch<float, int64_t>), g, t, 0, cap, b->d_items, b->d_first); break;
+      case 2: hipLaunchKernelGGL((k_batch<double, int32_t>), g, t, 0, cap, b->d_items, b->d_first); break;
+      default: hipLaunchKernelGGL((k_batch<double, int64_t>), g, t, 0, cap, b->d_items, b->d_first); break;
+    }
   }
   if ((e = hipStreamEndCapture(cap, &b->graph)) != hipSuccess) goto hip_error;
   if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) goto hip_error;
