@@ -192,6 +192,81 @@ __global__ __launch_bounds__(256 * KG, 1) void k_gemm_splitk(const T *__restrict
   }
 }
 
+// Small grids with a contraction of at most 512: one 32 x 32 tile per
+// workgroup of 16 waves, wave w taking k = 32 w .. 32 w + 31 of all four
+// 16 x 16 blocks. Fragments go from memory straight into registers: in MFMA
+// step s (of 8) the lanes 16 c + r (c = 0..3) supply k = 32 w + 8 c + s (any
+// assignment of k to lanes and steps gives the same sum, as long as A and B
+// use the same one), so a lane's A values of one block are 8 consecutive k
+// (16-byte vectors) and its B values 8 rows of one column (each row read by
+// 16 lanes as one run). Every load is issued before the first MFMA: one
+// memory round trip per tile, no LDS staging, no barrier until the partial
+// tiles are summed through LDS in wave order (deterministic).
+template <typename T>
+__global__ __launch_bounds__(1024, 1) void k_gemm_kslice(const T *__restrict__ A, const T *__restrict__ B,
+                                                         T *__restrict__ D, int64_t M, int64_t K, int64_t N,
+                                                         int64_t tiles_m, int64_t tiles_n) {
+  using MF = Mfma16<T>;
+  using acc_t = typename MF::acc_t;
+  constexpr int V = 16 / (int)sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(V)));
+  __shared__ T part[16][32 * 32];
+  int64_t tm, tn;
+  grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
+  const int64_t m0 = tm * 32, n0 = tn * 32;
+  const int lane = threadIdx.x % kWave, w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int r = lane % 16, c = lane / 16;
+  const int64_t kb = 32 * w + 8 * c;  // this lane's first k
+  // A: rows m0 + 16 ib + r, k = kb .. kb + 7 (K % V == 0: a vector is wholly
+  // inside or past K). B: rows kb .. kb + 7, column n0 + 16 jb + r.
+  vec_t av[2][8 / V];
+  T bv[2][8];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib) {
+    const int64_t row = m0 + 16 * ib + r;
+#pragma unroll
+    for (int q = 0; q < 8 / V; ++q) {
+      const int64_t k = kb + V * q;
+      av[ib][q] = (row < M && k < K) ? *(const vec_t *)(A + row * K + k) : vec_t{};
+    }
+  }
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb) {
+    const int64_t col = n0 + 16 * jb + r;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int64_t k = kb + s;
+      bv[jb][s] = (col < N && k < K) ? B[k * N + col] : T(0);
+    }
+  }
+  acc_t acc[2][2];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[ib][jb][v] = T(0);
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = MF::run(av[ib][s / V][s % V], bv[jb][s], acc[ib][jb]);
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) part[w][(16 * ib + MF::row(lane, v)) * 32 + 16 * jb + r] = acc[ib][jb][v];
+  __syncthreads();
+  const int e = threadIdx.x;  // one element of the 32 x 32 tile per thread
+  T sum = part[0][e];
+#pragma unroll
+  for (int q = 1; q < 16; ++q) sum += part[q][e];
+  const int64_t gm = m0 + e / 32, gn = n0 + e % 32;
+  if (gm < M && gn < N) D[gm * N + gn] = sum;
+}
+
 // Every offset of a tile of M x K . K x N (extents padded by a 128 tile) fits
 // in 31 bits.
 static bool fits_int32(int64_t M, int64_t K, int64_t N) {
@@ -218,6 +293,14 @@ static hipError_t launch_t(const T *A, const T *B, T *D, int64_t M, int64_t K, i
     if constexpr (!TA && !TB && !GEN) {
       // Fewer 32 x 32 tiles than SIMDs and a contraction of at least 256:
       // split it over four wave groups per tile.
+      if constexpr (VEC) {
+        // A contraction of 256..512: every fragment in registers at once.
+        if (automatic && tmn * tnn < 1024 && K >= 256 && K <= 512) {
+          hipLaunchKernelGGL((k_gemm_kslice<T>), dim3((unsigned)(tmn * tnn)), dim3(1024), 0, s, A, B, D, M, K, N,
+                             tmn, tnn);
+          return hipGetLastError();
+        }
+      }
       if (automatic && tmn * tnn < 1024 && K >= 256) {
         // 32-wide panels, two in flight per thread beyond the one in LDS.
         hipLaunchKernelGGL((k_gemm_splitk<T, 4, 32, 2, VEC>), dim3((unsigned)(tmn * tnn)), dim3(1024), 0, s, A, B, D,

@@ -1057,7 +1057,31 @@ FP32_GEMM_VARIANTS = [
     ((3, 2, 70), 2, (70, 5, 9), 0, "rank 3 . rank 3"),
     ((200, 1000), 1, (1000, 132), 0, "32x32 tiles, k split over 4 wave groups, vector panels"),
     ((97, 333), 1, (333, 61), 0, "32x32 tiles, k split over 4 wave groups, scalar panels"),
+    ((200, 512), 1, (512, 132), 0, "32x32 tiles, k sliced over 16 waves, K = 512"),
+    ((97, 300), 1, (300, 61), 0, "32x32 tiles, k sliced over 16 waves, K = 300 (last waves past K)"),
+    ((33, 256), 1, (256, 33), 0, "32x32 tiles, k sliced over 16 waves, K = 256, one row and column past a tile"),
 ]
+
+
+# FP64 small grids: the k-sliced kernel (K = 256..512, 16-byte aligned rows)
+# and the kernel that splits k over four wave groups (longer K, or rows that
+# are not 16-byte multiples), on small integers (exact in FP64).
+FP64_SMALL_GRID = [
+    ((512, 512), (512, 512), "k sliced, the 512^3 workload shape"),
+    ((200, 300), (300, 130), "k sliced, K = 300"),
+    ((33, 256), (256, 40), "k sliced, K = 256, ragged"),
+    ((200, 1000), (1000, 132), "k split over 4 wave groups, vector panels"),
+    ((97, 333), (333, 61), "k split over 4 wave groups, scalar panels"),
+]
+
+
+@pytest.mark.parametrize("case", FP64_SMALL_GRID, ids=[c[2] for c in FP64_SMALL_GRID])
+def test_fp64_small_grid_exact_integers(case):
+    sa, sb, what = case
+    rng = np.random.default_rng(163)
+    a, b = mi.small_int_f64(rng, sa, 8), mi.small_int_f64(rng, sb, 8)
+    say("fp64 exact", what, sa, sb)
+    eq(host(G.inner(gpu(a), gpu(b))), a @ b)
 
 
 @pytest.mark.parametrize("case", FP32_GEMM_VARIANTS, ids=[c[4] for c in FP32_GEMM_VARIANTS])
