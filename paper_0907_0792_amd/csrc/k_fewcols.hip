@@ -18,6 +18,8 @@
 // fold (wrapping + and * included) and FP max/min.
 #pragma clang fp contract(off)
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -169,6 +171,108 @@ __global__ __launch_bounds__(256) void k_fewcols(const T *__restrict__ A, const 
   }
 }
 
+// B resident in LDS: when all of B (K rows of NC elements) fits in 128 KiB,
+// one workgroup of 16 waves per CU stages it once, with the same permuted row
+// placement, and then streams rows of A with no further barrier: wave groups
+// of R rows are taken round-robin, each lane loading 16-byte runs of A one
+// span ahead of the fold. No B chunk is re-staged per 256 l (no per-chunk
+// loads, LDS stores or barriers).
+constexpr int kResidentBytes = 128 * 1024;
+
+template <typename T, int OP1, int OP2, int NC, int R>
+__global__ __launch_bounds__(1024, 1) void k_fewcols_resident(const T *__restrict__ A, const T *__restrict__ B,
+                                                              T *__restrict__ D, int64_t M, int K, int N) {
+  constexpr int VW = 16 / (int)sizeof(T), SPAN = kWave * VW;
+  constexpr int RV = (NC * (int)sizeof(T) + 15) / 16;  // 16-byte reads per staged row
+  typedef __attribute__((__vector_size__(16))) T vec_t;
+  __shared__ __attribute__((aligned(16))) T Bs[kResidentBytes / sizeof(T)];
+  const int tid = threadIdx.x, lane = tid % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  auto pos = [](int l) { return (l / SPAN) * SPAN + (l % VW) * kWave + (l % SPAN) / VW; };
+#pragma unroll 8
+  for (int e = tid; e < K * NC; e += 1024) {
+    const int l = e / NC, c = e % NC;
+    Bs[pos(l) * NC + c] = c < N ? B[(int64_t)l * N + c] : T(0);
+  }
+  __syncthreads();
+  const int nspan = K / SPAN;
+  const int64_t groups = (M + R - 1) / R;
+  for (int64_t g = (int64_t)blockIdx.x * 16 + wave; g < groups; g += (int64_t)gridDim.x * 16) {
+    const T *a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = g * R + r < M ? g * R + r : M - 1;  // rows past M repeat row M - 1, never stored
+      a[r] = A + i * K + VW * lane;
+    }
+    T acc[R][NC];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[r][c] = fold_identity<OP1, T>();
+    vec_t x[R], xn[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = *(const vec_t *)a[r];
+    for (int sp = 0; sp < nspan; ++sp) {
+      if (sp + 1 < nspan) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) xn[r] = *(const vec_t *)(a[r] + (sp + 1) * SPAN);
+      }
+#pragma unroll
+      for (int u = 0; u < VW; u += 2) {
+        T b[2][RV * VW];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          const T *row = &Bs[(sp * SPAN + (u + w) * kWave + lane) * NC];
+          if constexpr (NC * sizeof(T) >= 16) {
+#pragma unroll
+            for (int q = 0; q < RV; ++q) {
+              const vec_t v = *(const vec_t *)(row + q * VW);
+#pragma unroll
+              for (int e = 0; e < VW; ++e) b[w][q * VW + e] = v[e];
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) b[w][c] = row[c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (c < N) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+              acc[r][c] = fold_pair<OP1>(acc[r][c], apply_op<OP2>(x[r][u], b[0][c]), apply_op<OP2>(x[r][u + 1], b[1][c]));
+          }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = xn[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int m = kWave / 2; m >= 1; m /= 2) acc[r][c] = apply_op<OP1>(acc[r][c], __shfl_xor(acc[r][c], m));
+    if (lane == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (g * R + r < M && c < N) D[(g * R + r) * N + c] = acc[r][c];
+    }
+  }
+}
+
+int cu_count() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    cached[dev] = (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) ? n : 256;
+  }
+  return cached[dev];
+}
+
 // Rows per wave (each staged B row, read as 16-byte vectors, feeds R terms
 // per value): 4, measured on int32 (max,+) 65536 x 4096 . 4096 x 8 over ten
 // back-to-back calls (0.234 ms; 2 rows: 0.247 ms).
@@ -182,6 +286,17 @@ void launch_ncr(const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N, h
   constexpr int R = rows_per_wave<T, NC>();
   const int64_t blocks = (M + 4 * R - 1) / (4 * R);
   const int vec = ((uintptr_t)A % 16) == 0 && K % (16 / (int64_t)sizeof(T)) == 0;
+  constexpr int64_t SPAN = kWave * (16 / (int64_t)sizeof(T));
+  if (vec && K % SPAN == 0 && K * NC * (int64_t)sizeof(T) <= kResidentBytes) {
+    // 16 waves per CU leave 128 registers per lane: fewer rows per wave for
+    // wide (FP64, or 16-column) rows.
+    constexpr int RR = (sizeof(T) * NC > 64) ? 1 : (sizeof(T) * NC > 32) ? 2 : R;
+    const int64_t groups = (M + RR - 1) / RR;
+    const int64_t grid = std::min<int64_t>(cu_count(), (groups + 15) / 16);
+    hipLaunchKernelGGL((k_fewcols_resident<T, OP1, OP2, NC, RR>), dim3((unsigned)grid), dim3(1024), 0, s, A, B, D,
+                       M, (int)K, (int)N);
+    return;
+  }
   hipLaunchKernelGGL((k_fewcols<T, OP1, OP2, NC, R>), dim3((unsigned)blocks), dim3(256), 0, s, A, B, D, M, K,
                      (int)N, vec);
 }

@@ -300,7 +300,11 @@ def test_few_columns_wave_reduction_bit_exact(dt):
     rng = np.random.default_rng(111)
     folds = FOLD_I if dt == np.int32 else ["max", "min"]
     elems = ELEM_I if dt == np.int32 else ELEM_F
-    for M, K, N in [(300, 1000, 1), (257, 777, 3), (5, 4100, 16), (1, 256, 7), (33, 300, 4), (9, 513, 9)]:
+    # The first six shapes take the chunked kernel (or, for K = 256, B
+    # resident in LDS); the last five keep all of B resident in LDS (K a
+    # multiple of one 16-byte run per lane of a wave, B at most 128 KiB).
+    for M, K, N in [(300, 1000, 1), (257, 777, 3), (5, 4100, 16), (1, 256, 7), (33, 300, 4), (9, 513, 9),
+                    (300, 512, 1), (257, 1024, 3), (33, 768, 5), (100, 1024, 9), (70, 2048, 16)]:
         a = rand(rng, (M, K), dt)
         b = rand(rng, (K, N), dt)
         ga, gb = gpu(a), gpu(b)
