@@ -214,9 +214,11 @@ static hipError_t dispatch_op2(moa_op op2, const T *A, const T *B, T *D, int64_t
   return hipErrorInvalidValue;
 }
 
+// Every op pair for one dtype and run count (external linkage, so that the
+// large instance sets can be compiled in separate units).
 template <typename T, int R>
-static hipError_t dispatch_op1(moa_op op1, moa_op op2, const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N,
-                               hipStream_t s) {
+hipError_t skinny_dispatch(moa_op op1, moa_op op2, const T *A, const T *B, T *D, int64_t M, int64_t K, int64_t N,
+                           hipStream_t s) {
   switch (op1) {
     case MOA_ADD: return dispatch_op2<T, MOA_ADD, R>(op2, A, B, D, M, K, N, s);
     case MOA_MUL: return dispatch_op2<T, MOA_MUL, R>(op2, A, B, D, M, K, N, s);
@@ -241,11 +243,11 @@ hipError_t skinny_launch_r(moa_dtype dt, moa_op op1, moa_op op2, const void *A, 
                            int64_t K, int64_t N, hipStream_t s) {
   switch (dt) {
     case MOA_F64:
-      return dispatch_op1<double, R>(op1, op2, (const double *)A, (const double *)B, (double *)D, M, K, N, s);
+      return skinny_dispatch<double, R>(op1, op2, (const double *)A, (const double *)B, (double *)D, M, K, N, s);
     case MOA_F32:
-      return dispatch_op1<float, R>(op1, op2, (const float *)A, (const float *)B, (float *)D, M, K, N, s);
+      return skinny_dispatch<float, R>(op1, op2, (const float *)A, (const float *)B, (float *)D, M, K, N, s);
     case MOA_I32:
-      return dispatch_op1<int32_t, R>(op1, op2, (const int32_t *)A, (const int32_t *)B, (int32_t *)D, M, K, N, s);
+      return skinny_dispatch<int32_t, R>(op1, op2, (const int32_t *)A, (const int32_t *)B, (int32_t *)D, M, K, N, s);
     default: break;
   }
   return hipErrorInvalidValue;
