@@ -29,10 +29,14 @@ struct Mfma16<float> {
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane / 16) + v; }
 };
 
-// LDS bytes of one tile's panels (A: BK x (BM + 2), B: BK x (BN + 2)).
+// LDS bytes of one tile's panels, for either layout of each operand
+// (k-major: BK x (side + 2); row-major: side x (BK + 16 bytes)).
 template <typename T, int WBM, int WBN, int BK>
 constexpr int gemm_tile_lds_bytes() {
-  return (int)sizeof(T) * BK * (32 * WBM + 2 + 32 * WBN + 2);
+  constexpr int PA = 16 / (int)sizeof(T);
+  constexpr int a = BK * (32 * WBM + 2) > 32 * WBM * (BK + PA) ? BK * (32 * WBM + 2) : 32 * WBM * (BK + PA);
+  constexpr int b = BK * (32 * WBN + 2) > 32 * WBN * (BK + PA) ? BK * (32 * WBN + 2) : 32 * WBN * (BK + PA);
+  return (int)sizeof(T) * (a + b);
 }
 
 // One BM x BN tile of D = A . B (BM = 32*WBM, BN = 32*WBN), computed by the
@@ -60,7 +64,7 @@ constexpr int gemm_tile_lds_bytes() {
 // one buffer sized for the largest instead of one per shape; gemm_tile below
 // declares its own.
 template <typename T, bool TA, bool TB, int WBM, int WBN, int BK = 16, bool GEN = false, bool SKIP = false,
-          bool VEC = false, typename I = int64_t>
+          bool VEC = false, typename I = int64_t, bool RCL = false>
 __device__ __forceinline__ void gemm_tile_at(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
                                              I M, I K, I N, I m0, I n0, I Qa, I Qb, unsigned char *smem) {
   using MF = Mfma16<T>;
@@ -70,8 +74,21 @@ __device__ __forceinline__ void gemm_tile_at(const T *__restrict__ A, const T *_
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
   constexpr int V = VEC ? 16 / (int)sizeof(T) : 1;  // elements per load
   typedef __attribute__((__vector_size__(V * sizeof(T)))) T vec_t;
+  // Panel layouts. With RCL, an operand whose rows run along k in memory (A
+  // as stored, or B read as stored N x K; not the strided views) is staged
+  // row-major, rows of BK padded by 16 bytes: the loaded vectors are stored
+  // whole (no transposing scatter of 4-byte stores, whose bank conflicts
+  // stall the LDS), and a fragment is read as 16-byte vectors (below). It
+  // keeps a row-major fragment's values live across steps, so it is enabled
+  // only where the registers allow. Every other operand is staged k-major,
+  // rows of the tile side padded by 2 elements.
+  constexpr bool A_RC = RCL && !TA && !GEN, B_RC = RCL && TB && !GEN;
+  constexpr int PA = 16 / (int)sizeof(T);
+  constexpr int ABYTES = (int)sizeof(T) * (A_RC ? BM * (BK + PA) : BK * (BM + PAD));
   T(*As)[BM + PAD] = reinterpret_cast<T(*)[BM + PAD]>(smem);
-  T(*Bs)[BN + PAD] = reinterpret_cast<T(*)[BN + PAD]>(smem + sizeof(T) * BK * (BM + PAD));
+  T(*Ar)[BK + PA] = reinterpret_cast<T(*)[BK + PA]>(smem);
+  T(*Bs)[BN + PAD] = reinterpret_cast<T(*)[BN + PAD]>(smem + ABYTES);
+  T(*Br)[BK + PA] = reinterpret_cast<T(*)[BK + PA]>(smem + ABYTES);
 
   const int tid = threadIdx.x, lane = tid % kWave, wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const int wm = wave / 2, wn = wave % 2;
@@ -170,40 +187,97 @@ __device__ __forceinline__ void gemm_tile_at(const T *__restrict__ A, const T *_
 #pragma unroll
     for (int e = 0; e < EA / V; ++e) {
       const int f = tid + 256 * e;
+      if constexpr (A_RC) {
+        *(vec_t *)&Ar[f / (BK / V)][(f % (BK / V)) * V] = ra[e];
+      } else {
 #pragma unroll
-      for (int u = 0; u < V; ++u) {
-        if constexpr (!TA)
-          As[(f % (BK / V)) * V + u][f / (BK / V)] = ra[e][u];
-        else
-          As[f / (BM / V)][(f % (BM / V)) * V + u] = ra[e][u];
+        for (int u = 0; u < V; ++u) {
+          if constexpr (!TA)
+            As[(f % (BK / V)) * V + u][f / (BK / V)] = ra[e][u];
+          else
+            As[f / (BM / V)][(f % (BM / V)) * V + u] = ra[e][u];
+        }
       }
     }
 #pragma unroll
     for (int e = 0; e < EB / V; ++e) {
       const int f = tid + 256 * e;
+      if constexpr (B_RC) {
+        *(vec_t *)&Br[f / (BK / V)][(f % (BK / V)) * V] = rb[e];
+      } else {
 #pragma unroll
-      for (int u = 0; u < V; ++u) {
-        if constexpr (!TB)
-          Bs[f / (BN / V)][(f % (BN / V)) * V + u] = rb[e][u];
-        else
-          Bs[(f % (BK / V)) * V + u][f / (BK / V)] = rb[e][u];
+        for (int u = 0; u < V; ++u) {
+          if constexpr (!TB)
+            Bs[f / (BN / V)][(f % (BN / V)) * V + u] = rb[e][u];
+          else
+            Bs[(f % (BK / V)) * V + u][f / (BK / V)] = rb[e][u];
+        }
       }
     }
   };
 
+  // The panel's BK / 4 matrix-core steps assign k to lanes so that a
+  // row-major operand's fragment is contiguous: in step s the lanes 16 g + r
+  // (g = 0..3) supply k = g BK / 4 + s, so lane (r, g) needs k = g BK / 4 ..
+  // g BK / 4 + BK / 4 - 1 of its row, read HS at a time as one 16-byte vector
+  // (any assignment gives the same sum, as long as A and B use the same one).
+  // k-major operands are read one element per step, as before.
+  constexpr int KS = BK / 4, HS = 16 / (int)sizeof(T);
+  typedef __attribute__((__vector_size__(16))) T v16_t;
   auto compute = [&]() {
+    if constexpr (!A_RC && !B_RC) {
+      // Both k-major: step k4 / 4 takes k = k4 + l / 16 in lane l.
 #pragma unroll
-    for (int k4 = 0; k4 < BK; k4 += 4) {
-      T a[WBM], b[WBN];
+      for (int k4 = 0; k4 < BK; k4 += 4) {
+        T a[WBM], b[WBN];
 #pragma unroll
-      for (int i = 0; i < WBM; ++i) a[i] = As[k4 + lane / 16][wm * (BM / 2) + i * 16 + lane % 16];
+        for (int i = 0; i < WBM; ++i) a[i] = As[k4 + lane / 16][wm * (BM / 2) + i * 16 + lane % 16];
 #pragma unroll
-      for (int j = 0; j < WBN; ++j) b[j] = Bs[k4 + lane / 16][wn * (BN / 2) + j * 16 + lane % 16];
+        for (int j = 0; j < WBN; ++j) b[j] = Bs[k4 + lane / 16][wn * (BN / 2) + j * 16 + lane % 16];
 #pragma unroll
-      for (int i = 0; i < WBM; ++i)
+        for (int i = 0; i < WBM; ++i)
 #pragma unroll
-        for (int j = 0; j < WBN; ++j)
-          if (!SKIP || (i < nbm && j < nbn)) acc[i][j] = MF::run(a[i], b[j], acc[i][j]);
+          for (int j = 0; j < WBN; ++j)
+            if (!SKIP || (i < nbm && j < nbn)) acc[i][j] = MF::run(a[i], b[j], acc[i][j]);
+      }
+      return;
+    }
+    const int r = lane % 16, g = lane / 16;
+#pragma unroll
+    for (int c = 0; c < KS / HS; ++c) {
+      [[maybe_unused]] v16_t av[A_RC ? WBM : 1], bv[B_RC ? WBN : 1];
+      if constexpr (A_RC) {
+#pragma unroll
+        for (int i = 0; i < WBM; ++i) av[i] = *(const v16_t *)&Ar[wm * (BM / 2) + i * 16 + r][g * KS + c * HS];
+      }
+      if constexpr (B_RC) {
+#pragma unroll
+        for (int j = 0; j < WBN; ++j) bv[j] = *(const v16_t *)&Br[wn * (BN / 2) + j * 16 + r][g * KS + c * HS];
+      }
+#pragma unroll
+      for (int t = 0; t < HS; ++t) {
+        const int kk = g * KS + c * HS + t;
+        T a[WBM], b[WBN];
+#pragma unroll
+        for (int i = 0; i < WBM; ++i) {
+          if constexpr (A_RC)
+            a[i] = av[i][t];
+          else
+            a[i] = As[kk][wm * (BM / 2) + i * 16 + r];
+        }
+#pragma unroll
+        for (int j = 0; j < WBN; ++j) {
+          if constexpr (B_RC)
+            b[j] = bv[j][t];
+          else
+            b[j] = Bs[kk][wn * (BN / 2) + j * 16 + r];
+        }
+#pragma unroll
+        for (int i = 0; i < WBM; ++i)
+#pragma unroll
+          for (int j = 0; j < WBN; ++j)
+            if (!SKIP || (i < nbm && j < nbn)) acc[i][j] = MF::run(a[i], b[j], acc[i][j]);
+      }
     }
   };
 
@@ -231,11 +305,11 @@ __device__ __forceinline__ void gemm_tile_at(const T *__restrict__ A, const T *_
 }
 
 template <typename T, bool TA, bool TB, int WBM, int WBN, int BK = 16, bool GEN = false, bool SKIP = false,
-          bool VEC = false, typename I = int64_t>
+          bool VEC = false, typename I = int64_t, bool RCL = false>
 __device__ __forceinline__ void gemm_tile(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ D,
                                           I M, I K, I N, I m0, I n0, I Qa = 1, I Qb = 1) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[gemm_tile_lds_bytes<T, WBM, WBN, BK>()];
-  gemm_tile_at<T, TA, TB, WBM, WBN, BK, GEN, SKIP, VEC, I>(A, B, D, M, K, N, m0, n0, Qa, Qb, smem);
+  gemm_tile_at<T, TA, TB, WBM, WBN, BK, GEN, SKIP, VEC, I, RCL>(A, B, D, M, K, N, m0, n0, Qa, Qb, smem);
 }
 
 }  // namespace moa

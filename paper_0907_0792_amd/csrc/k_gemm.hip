@@ -41,7 +41,10 @@ __global__ __launch_bounds__(256, (gemm_min_blocks<T, WBM, VEC, I>())) void k_ge
   grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
   // FP32 MFMAs run at twice the FP64 rate: 32-wide k panels halve the
   // barriers and panel stores per flop.
-  gemm_tile<T, TA, TB, WBM, WBN, sizeof(T) == 4 ? 32 : 16, GEN, false, VEC, I>(
+  // Row-major staging of k-contiguous operands for the FP64 vector-panel
+  // tiles (their registers allow it; the FP32 128 x 128 tiles would spill).
+  constexpr bool RCL = sizeof(T) == 8 && VEC;
+  gemm_tile<T, TA, TB, WBM, WBN, sizeof(T) == 4 ? 32 : 16, GEN, false, VEC, I, RCL>(
       A, B, D, (I)M, (I)K, (I)N, (I)(tm * 32 * WBM), (I)(tn * 32 * WBN), (I)Qa, (I)Qb);
 }
 
@@ -413,9 +416,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_grad_pair(GemmJob j0, GemmJob j
   int64_t tm, tn;
   if ((int64_t)blockIdx.x < n0) {
     grouped_tile(xcd_swizzle(blockIdx.x, n0), j0.tiles_m, j0.tiles_n, 8, tm, tn);
-    gemm_tile_at<T, false, true, WBM, WBN, BK, false, false, VEC>((const T *)j0.A, (const T *)j0.B, (T *)j0.D, j0.M,
-                                                                   j0.K, j0.N, tm * 32 * WBM, tn * 32 * WBN,
-                                                                   (int64_t)1, (int64_t)1, smem);
+    // dA = G . B^T reads both operands k-contiguous: row-major staging where
+    // the registers allow it (tiles up to 64 x 64).
+    gemm_tile_at<T, false, true, WBM, WBN, BK, false, false, VEC, int64_t, VEC && WBM <= 2>(
+        (const T *)j0.A, (const T *)j0.B, (T *)j0.D, j0.M, j0.K, j0.N, tm * 32 * WBM, tn * 32 * WBN, (int64_t)1,
+        (int64_t)1, smem);
   } else {
     const int64_t b = blockIdx.x - n0, n1 = j1.tiles_m * j1.tiles_n;
     grouped_tile(xcd_swizzle(b, n1), j1.tiles_m, j1.tiles_n, 8, tm, tn);
