@@ -13,6 +13,9 @@
 //   1: 64 x 64 tiles (2 x 2 blocks per wave)
 // The table maps (M, N, K) size buckets to a variant; moa_batch_autotune
 // fills it by timing both variants on synthetic problems of each bucket.
+// FP32 batches whose operands allow 32-bit byte offsets run the LDS-fed
+// tile (batch_tile_lds: buffer loads straight into an LDS ring); FP64 and
+// larger FP32 batches run the register-staged tile of gemm_tile.hpp.
 #include <stdio.h>
 #include <string.h>
 
