@@ -40,11 +40,17 @@ __global__ __launch_bounds__(256, (gemm_min_blocks<T, WBM, VEC, I>())) void k_ge
   int64_t tm, tn;
   grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
   // FP32 MFMAs run at twice the FP64 rate: 32-wide k panels halve the
-  // barriers and panel stores per flop.
+  // barriers and panel stores per flop (below: except one tile).
   // Row-major staging of k-contiguous operands for the FP64 vector-panel
-  // tiles (their registers allow it; the FP32 128 x 128 tiles would spill).
-  constexpr bool RCL = sizeof(T) == 8 && VEC;
-  gemm_tile<T, TA, TB, WBM, WBN, sizeof(T) == 4 ? 32 : 16, GEN, false, VEC, I, RCL>(
+  // tiles, and for the FP32 128 x 128 tile with 32-bit indices, there with
+  // 16-wide panels: its four workgroups per CU leave 128 registers, which
+  // 32-wide panels plus the longer-lived fragments would exceed (FP32
+  // 8192^3 8.57 -> 8.45 ms, 4096 x 512 . 512 x 4096 forward + backward
+  // 0.546 -> 0.541 ms, same box). The other FP32 tiles keep 32-wide k-major
+  // panels.
+  constexpr bool F32I = sizeof(T) == 4 && sizeof(I) == 4 && WBM == 4 && VEC;
+  constexpr bool RCL = (sizeof(T) == 8 && VEC) || F32I;
+  gemm_tile<T, TA, TB, WBM, WBN, (sizeof(T) == 4 && !F32I) ? 32 : 16, GEN, false, VEC, I, RCL>(
       A, B, D, (I)M, (I)K, (I)N, (I)(tm * 32 * WBM), (I)(tn * 32 * WBN), (I)Qa, (I)Qb);
 }
 
