@@ -735,6 +735,31 @@ class _tile_variant:
 
 
 @pytest.mark.parametrize("variant", BATCH_VARIANTS)
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_batch_degenerate_and_ragged_problems(variant, dt):
+    # Empty sums (K = 0: the result is all zeros), empty results (M or N = 0:
+    # nothing written), 1 x 1 x 1, K that is not a multiple of the 16-wide
+    # panels, M and N one past a tile, and a full 64 x 64 tile, in one batch.
+    # Small integers: exact sums, compared element by element. FP32 batches
+    # run the LDS-fed tile, FP64 the register-staged one.
+    rng = np.random.default_rng(171)
+    shapes = [((5, 0), (0, 7)), ((0, 9), (9, 4)), ((6, 9), (9, 0)), ((1, 1), (1, 1)), ((3, 17), (17, 2)),
+              ((33, 31), (31, 65)), ((64, 512), (512, 64)), ((65, 16), (16, 33)), ((2, 3, 47), (47, 5, 2))]
+    a_s = [mi.small_int_f64(rng, sa, 8).astype(dt) for sa, _ in shapes]
+    b_s = [mi.small_int_f64(rng, sb, 8).astype(dt) for _, sb in shapes]
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    pool = GuardPool([(moa.inner_shape(sa, sb), tdt) for sa, sb in shapes])
+    say("batch degenerate and ragged", np.dtype(dt).name, "tile variant", variant)
+    with _tile_variant(variant):
+        bt = moa.Batch([gpu(a) for a in a_s], [gpu(b) for b in b_s], pool.t)
+    bt.run()
+    pool.check("degenerate batch")
+    for a, b, d in zip(a_s, b_s, pool.t):
+        eq(host(d), np.tensordot(a.astype(np.float64), b.astype(np.float64), axes=([a.ndim - 1], [0])).astype(dt))
+    bt.close()
+
+
+@pytest.mark.parametrize("variant", BATCH_VARIANTS)
 def test_batch_wide_problem_64bit_offsets(variant):
     # A problem whose padded extents pass 2^31 offsets makes the whole batch
     # use 64-bit tile index arithmetic. Small integer entries: exact sums.
