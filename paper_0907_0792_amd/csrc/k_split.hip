@@ -53,6 +53,9 @@ struct Layout {
   static constexpr bool kWide = S <= 5;
   static constexpr int WMW = kWide ? 4 : 2, WNW = kWide ? 2 : (S <= 6 ? 4 : 2), WN = kWide ? 2 : 1;
   static constexpr int SKB = kWide ? 1 : 2, NBUF = kWide ? 3 : 2;
+  // The pipelined loop (buffer loads into LDS) for the wide layout; its
+  // per-stream descriptors need the stream's slice bytes below 2^31.
+  static constexpr bool PIPE = kWide;
   using C = split::Cfg<S, WMW, WNW, WN, SKB, NBUF>;
 };
 
@@ -405,8 +408,14 @@ hipError_t launch_multiply_s(const SplitPlan &p, double *D, void *ws, hipStream_
   const int64_t KB = p.Kp / 16;
   using L = Layout<S>;
   const int64_t tmn = p.Mp / L::C::BM, tnn = p.Np / L::C::BN;
-  hipLaunchKernelGGL((split::k_split_gemm<S, L::WMW, L::WNW, L::WN, L::SKB, L::NBUF, 1>), dim3((unsigned)(tmn * tnn)),
-                     dim3(L::C::kThreads), 0, s, Apk, Bpk, rowmax, colmax, D, p.M, p.N, KB, tmn, tnn);
+  if (L::PIPE && KB * S * 64 * (int64_t)sizeof(bf16x8) < ((int64_t)1 << 31))
+    hipLaunchKernelGGL((split::k_split_gemm<S, L::WMW, L::WNW, L::WN, L::SKB, L::NBUF, 1, L::PIPE>),
+                       dim3((unsigned)(tmn * tnn)), dim3(L::C::kThreads), 0, s, Apk, Bpk, rowmax, colmax, D, p.M, p.N,
+                       KB, tmn, tnn);
+  else
+    hipLaunchKernelGGL((split::k_split_gemm<S, L::WMW, L::WNW, L::WN, L::SKB, L::NBUF, 1, false>),
+                       dim3((unsigned)(tmn * tnn)), dim3(L::C::kThreads), 0, s, Apk, Bpk, rowmax, colmax, D, p.M, p.N,
+                       KB, tmn, tnn);
   return hipGetLastError();
 }
 

@@ -38,6 +38,13 @@
 // of one 32-column block at a time (a wave with WN = 2 holds 2S, not 3S,
 // fragments, which is what lets 32 x 64 wave blocks run at two waves per
 // SIMD).
+//
+// The 32 x 64 layout runs a pipelined form of the same loop (PIPE): copies are
+// buffer loads into LDS, each stage's barrier sits inside the stage before
+// it, and every fragment register is refilled right after its last MFMA, so
+// the fragment reads overlap the matrix-core work instead of stalling all
+// waves after each barrier. On the 8192^3, 5-slice product it takes 11.85-11.90
+// ms against 12.45 ms for the plain loop (same box, same run).
 #pragma once
 
 #include <utility>
@@ -94,7 +101,14 @@ __device__ __forceinline__ int exponent_of_max(uint64_t bits) {
   return e;
 }
 
-template <int S, int WMW, int WNW, int WN, int SKB, int NBUF, int MINB>
+// 16 bytes per lane from base + voff + soff into LDS at dst + 16 * lane, by
+// a buffer load whose descriptor covers nbytes from base.
+__device__ __forceinline__ void copy16_to_lds(const void *base, int nbytes, void *dst, int voff, int soff) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(__builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nbytes, 0x00020000),
+                                           (__attribute__((address_space(3))) void *)dst, 16, voff, soff, 0, 0);
+}
+
+template <int S, int WMW, int WNW, int WN, int SKB, int NBUF, int MINB, bool PIPE = false>
 __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
     const bf16x8 *__restrict__ Apk, const bf16x8 *__restrict__ Bpk, const uint64_t *__restrict__ rowmax,
     const uint64_t *__restrict__ colmax, double *__restrict__ D, int64_t M, int64_t N, int64_t KB, int64_t tiles_m,
@@ -109,6 +123,7 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
   const int tid = threadIdx.x, lane = tid % 64;
   // Wave index as a wave-uniform (scalar) value, so chunk addresses are scalar.
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  __builtin_assume(wave >= 0 && wave < C::kWaves);
   const int wm = wave / WNW, wn = wave % WNW;
 
   // Per-wave chunk bases at stage 0, forced wave-uniform so they live in
@@ -217,17 +232,12 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
     for (int kbl = 0; kbl < SKB; ++kbl) mma_kb(buf, kbl);
   };
 
-  for (int i = 0; i < NBUF - 1; ++i)
-    if (i < nst) issue_stage(i, i);
-  // Groups of 64 k (K is padded to a multiple of 64): level 2 folds after
-  // every group, level 1 after every second, levels 0 and 3 (or the merged
-  // accumulator) after every fourth, separate levels from 4 up only after the
-  // last; every accumulator folds after the last group (a fold zeroes it).
-  const int64_t ngroups = nst / (4 / SKB);
-  for (int64_t g = 0; g < ngroups; ++g) {
-#pragma unroll
-    for (int i = 0; i < 4 / SKB; ++i) stage(g * (4 / SKB) + i);
-    const bool last = g + 1 == ngroups;
+  // Folds after the 64-k group g (K is padded to a multiple of 64): level 2
+  // after every group, level 1 after every second, levels 0 and 3 (or the
+  // merged accumulator) after every fourth, separate levels from 4 up only
+  // after the last; every accumulator folds after the last group (a fold
+  // zeroes it).
+  auto fold_group = [&](int64_t g, bool last) {
     if constexpr (L > 2) fold(2);
     if constexpr (L > 1)
       if ((g & 1) == 1 || last) fold(1);
@@ -238,6 +248,128 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
     if (last) {
 #pragma unroll
       for (int l = 4; l < L; ++l) fold(l);
+    }
+  };
+
+  if constexpr (PIPE) {
+    // Pipelined form for 32 x 64 wave blocks and one k block per stage. The
+    // stage barrier sits inside the previous stage, after the first round of
+    // its second column block: by then the wave has read every fragment of
+    // that stage into registers. Each fragment register is refilled for the
+    // next column block (or the next stage) right after its last MFMA, so
+    // the LDS reads run under the matrix-core work instead of in a burst
+    // after every barrier, when all waves would wait on them together.
+    // B fragment t is last used by the first MFMA of round S - 1 - t, A
+    // fragment r by the last MFMA of round r.
+    static_assert(WN == 2 && SKB == 1 && NBUF == 3, "pipelined form: 32 x 64 wave blocks, three 16-k stages");
+    auto a_at = [&](int buf, int s) -> const bf16x8 & { return lds[buf][(wm * S + s) * 64 + lane]; };
+    auto b_at = [&](int buf, int j, int t) -> const bf16x8 & {
+      return lds[buf][C::A_CH * 64 + ((wn * WN + j) * S + t) * 64 + lane];
+    };
+    // Stage x becomes readable: its copies are done (the next stage's may
+    // stay in flight), every wave has left the fragments of stage x - 1, and
+    // that buffer is refilled with stage x + 2.
+    // Copies by buffer loads into LDS: chunk stream q of this wave gets a
+    // descriptor at its stage-0 chunk covering its nst chunks (the host keeps
+    // that below 2^31 bytes); the stage offset goes in the scalar offset.
+    // With global_load_lds in flight the compiler cannot order LDS reads and
+    // turns every wait for one fragment into a wait for all of them.
+    const int stream_bytes = (int)(nst * (S * 64 * 16));
+    auto issue_buf = [&](int64_t st, int buf) {
+#pragma unroll
+      for (int q = 0; q < C::MAX_WAVE; ++q) {
+        const int c = wave + C::kWaves * q;
+        if (c >= C::ST_CH) break;
+        copy16_to_lds(cbase[q], stream_bytes, &lds[buf][c * 64], lane * 16, (int)st * (S * 64 * 16));
+      }
+    };
+    auto open_stage = [&](int64_t x) {
+      if (x + 1 < nst) {
+        if (wave < C::EXTRA)
+          __builtin_amdgcn_s_waitcnt(vmcnt_imm(C::MAX_WAVE));
+        else
+          __builtin_amdgcn_s_waitcnt(vmcnt_imm(C::PER_WAVE));
+      } else {
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+      }
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+      if (x + 2 < nst) issue_buf(x + 2, (int)((x + 2) % NBUF));
+    };
+    // The epilogue's kernel arguments are loaded here, before the loop: a
+    // scalar load still in flight would make every LDS wait in the loop a
+    // full drain (scalar loads complete out of order on the same counter).
+    asm volatile("" ::"s"(rowmax), "s"(colmax), "s"(D));
+    bf16x8 af[S], bfr[S];
+    issue_buf(0, 0);
+    if (1 < nst) issue_buf(1, 1);
+    open_stage(0);
+    // Same read order as the loop's refills, so the waits at the loop head
+    // are the same from both sides.
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      bfr[S - 1 - r] = b_at(0, 0, S - 1 - r);
+      af[r] = a_at(0, r);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    constexpr bool MG = C::MERGE;
+    // One stage; MORE: a next stage exists (every stage but the last), so
+    // the body has no data-dependent branches around its LDS reads.
+    auto run_stage = [&]<bool MORE>(int64_t st) {
+      const int buf = (int)(st % NBUF), nbuf = (int)((st + 1) % NBUF);
+      // Column block 0; its B fragments are replaced by block 1's.
+#pragma unroll
+      for (int r = 0; r < S; ++r)
+#pragma unroll
+        for (int d = S - 1; d >= r; --d) {
+          acc[acc_of<MG>(d)][0] = mfma_bf16(af[r], bfr[d - r], acc[acc_of<MG>(d)][0]);
+          if (d == S - 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            bfr[S - 1 - r] = b_at(buf, 1, S - 1 - r);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      // Column block 1, round 0 (it reads every B fragment).
+#pragma unroll
+      for (int d = S - 1; d >= 0; --d) acc[acc_of<MG>(d)][1] = mfma_bf16(af[0], bfr[d], acc[acc_of<MG>(d)][1]);
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (MORE) {
+        open_stage(st + 1);
+        bfr[S - 1] = b_at(nbuf, 0, S - 1);
+        af[0] = a_at(nbuf, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // Rounds 1.. of column block 1; fragments are replaced by the next
+      // stage's as they retire.
+#pragma unroll
+      for (int r = 1; r < S; ++r) {
+#pragma unroll
+        for (int d = S - 1; d >= r; --d) {
+          acc[acc_of<MG>(d)][1] = mfma_bf16(af[r], bfr[d - r], acc[acc_of<MG>(d)][1]);
+          if constexpr (MORE)
+            if (d == S - 1) {
+              __builtin_amdgcn_sched_barrier(0);
+              bfr[S - 1 - r] = b_at(nbuf, 0, S - 1 - r);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if constexpr (MORE) {
+          af[r] = a_at(nbuf, r);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if ((st & 3) == 3) fold_group(st >> 2, !MORE);
+    };
+    for (int64_t st = 0; st + 1 < nst; ++st) run_stage.template operator()<true>(st);
+    run_stage.template operator()<false>(nst - 1);
+  } else {
+    for (int i = 0; i < NBUF - 1; ++i)
+      if (i < nst) issue_stage(i, i);
+    const int64_t ngroups = nst / (4 / SKB);
+    for (int64_t g = 0; g < ngroups; ++g) {
+#pragma unroll
+      for (int i = 0; i < 4 / SKB; ++i) stage(g * (4 / SKB) + i);
+      fold_group(g, g + 1 == ngroups);
     }
   }
 
@@ -306,6 +438,7 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_i8(
   grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 4, tm, tn);
   const int tid = threadIdx.x, lane = tid % 64;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  __builtin_assume(wave >= 0 && wave < C::kWaves);
   const int wm = wave / WNW, wn = wave % WNW;
 
   auto issue_stage = [&](int64_t st, int buf) {
