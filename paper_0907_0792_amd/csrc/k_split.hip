@@ -344,8 +344,13 @@ hipError_t launch_multiply_i8(const SplitPlan &p, double *D, void *ws, hipStream
   const int64_t KB = p.Kp / 32;
   using C = split::i8::Cfg<S, 2, 4>;
   const int64_t tmn = p.Mp / C::BM, tnn = p.Np / C::BN;
-  hipLaunchKernelGGL((split::i8::k_split_gemm_i8<S, 2, 4>), dim3((unsigned)(tmn * tnn)), dim3(C::kThreads), 0, s,
-                     Apk, Bpk, rowmax, colmax, D, p.M, p.N, KB, tmn, tnn);
+  // Pipelined loop while a chunk stream's slice bytes stay below 2^31.
+  if (KB * S * 64 * 16 < ((int64_t)1 << 31))
+    hipLaunchKernelGGL((split::i8::k_split_gemm_i8<S, 2, 4, true>), dim3((unsigned)(tmn * tnn)), dim3(C::kThreads), 0,
+                       s, Apk, Bpk, rowmax, colmax, D, p.M, p.N, KB, tmn, tnn);
+  else
+    hipLaunchKernelGGL((split::i8::k_split_gemm_i8<S, 2, 4, false>), dim3((unsigned)(tmn * tnn)), dim3(C::kThreads), 0,
+                       s, Apk, Bpk, rowmax, colmax, D, p.M, p.N, KB, tmn, tnn);
   return hipGetLastError();
 }
 
@@ -376,6 +381,16 @@ hipError_t launch_multiply_f8(const SplitPlan &p, double *D, void *ws, hipStream
   const int64_t KB = p.Kp / 64;
   using C = split::f8::Cfg<S, 2, 2>;
   const int64_t tmn = p.Mp / C::BM, tnn = p.Np / C::BN;
+  // The pipelined kernel, one launch per slab of 4096 k, while a tile's slice
+  // bytes stay below 2^31 (its buffer descriptors' reach).
+  if (C::MBW * KB * S * 2048 < ((int64_t)1 << 31) && C::NBW * KB * S * 2048 < ((int64_t)1 << 31)) {
+    for (int64_t lo = 0; lo < KB; lo += split::f8::kFoldStages) {
+      const int64_t hi = KB - lo < split::f8::kFoldStages ? KB : lo + split::f8::kFoldStages;
+      hipLaunchKernelGGL((split::f8::k_split_gemm_f8_slab<S, 2, 2>), dim3((unsigned)(tmn * tnn)), dim3(C::kThreads),
+                         0, s, Apk, Bpk, rowmax, colmax, D, p.M, p.N, KB, tmn, tnn, lo, hi);
+    }
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((split::f8::k_split_gemm_f8<S, 2, 2>), dim3((unsigned)(tmn * tnn)), dim3(C::kThreads), 0, s,
                      Apk, Bpk, rowmax, colmax, D, p.M, p.N, KB, tmn, tnn);
   return hipGetLastError();

@@ -101,6 +101,21 @@ __device__ __forceinline__ int exponent_of_max(uint64_t bits) {
   return e;
 }
 
+// s_waitcnt immediate: at most n vector-memory operations outstanding and no
+// LDS/scalar operation outstanding.
+__host__ __device__ constexpr int vmcnt_lgkm0_imm(int n) { return 0x0070 | (n & 15) | ((n >> 4) << 14); }
+
+// A wave-uniform pointer as a scalar value. readfirstlane returns a signed
+// int: each half goes through uint32_t before widening, or a low half with
+// bit 31 set would sign-extend over the high half.
+template <typename T>
+__device__ __forceinline__ const T *uniform_ptr(const T *p) {
+  const uint64_t u = (uint64_t)p;
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  return (const T *)((hi << 32) | lo);
+}
+
 // 16 bytes per lane from base + voff + soff into LDS at dst + 16 * lane, by
 // a buffer load whose descriptor covers nbytes from base.
 __device__ __forceinline__ void copy16_to_lds(const void *base, int nbytes, void *dst, int voff, int soff) {
@@ -424,7 +439,7 @@ struct Cfg {
   static constexpr int EXTRA = ST_CH % kWaves;
 };
 
-template <int S, int WMW, int WNW>
+template <int S, int WMW, int WNW, bool PIPE = false>
 __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_i8(
     const intx4 *__restrict__ Apk, const intx4 *__restrict__ Bpk, const uint64_t *__restrict__ rowmax,
     const uint64_t *__restrict__ colmax, double *__restrict__ D, int64_t M, int64_t N, int64_t KB, int64_t tiles_m,
@@ -479,34 +494,124 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_i8(
   };
 
   const int64_t nst = KB;
-  issue_stage(0, 0);
-  if (1 < nst) issue_stage(1, 1);
-  for (int64_t st = 0; st < nst; ++st) {
-    const int buf = (int)(st % kNBuf);
-    // The copies of stage st + 1 may stay in flight.
-    if (st + 1 < nst) {
-      if (wave < C::EXTRA)
-        __builtin_amdgcn_s_waitcnt(0x0F70 | C::MAX_WAVE);
+  if constexpr (PIPE) {
+    // Pipelined form, as in the BF16 kernel: buffer loads into LDS (so the
+    // compiler can wait for one fragment at a time), the barrier of stage
+    // st + 1 after round 0 of stage st, and each fragment register refilled
+    // with the next stage's right after its last MFMA (B fragment t: first
+    // MFMA of round S - 1 - t; A fragment r: last MFMA of round r).
+    const intx4 *qbase[C::MAX_WAVE];
+#pragma unroll
+    for (int q = 0; q < C::MAX_WAVE; ++q) {
+      const int c = wave + C::kWaves * q;
+      const intx4 *p;
+      if (c < C::A_CH)
+        p = Apk + ((tm * C::MBW + c / S) * KB * S + c % S) * 64;
       else
-        __builtin_amdgcn_s_waitcnt(0x0F70 | C::PER_WAVE);
-    } else {
-      __builtin_amdgcn_s_waitcnt(0x0F70);
+        p = Bpk + ((tn * C::NBW + (c - C::A_CH) / S) * KB * S + (c - C::A_CH) % S) * 64;
+      qbase[q] = uniform_ptr(p);
     }
-    // Plain barrier (no fence): this stage is visible, and the buffer of
-    // stage st - 1 is free for stage st + 2.
-    __builtin_amdgcn_s_barrier();
-    if (st + 2 < nst) issue_stage(st + 2, (int)((st + 2) % kNBuf));
+    const int stream_bytes = (int)(nst * (S * 64 * 16));
+    auto issue_buf = [&](int64_t st, int buf) {
+#pragma unroll
+      for (int q = 0; q < C::MAX_WAVE; ++q) {
+        const int c = wave + C::kWaves * q;
+        if (c >= C::ST_CH) break;
+        copy16_to_lds(qbase[q], stream_bytes, &lds[buf][c * 64], lane * 16, (int)st * (S * 64 * 16));
+      }
+    };
+    // Stage x becomes readable: its copies are done (the next stage's may
+    // stay in flight) and, after this wave's LDS reads have drained, every
+    // wave has left the buffer that now takes stage x + 2.
+    auto open_stage = [&](int64_t x) {
+      if (x + 1 < nst) {
+        if (wave < C::EXTRA)
+          __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(C::MAX_WAVE));
+        else
+          __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(C::PER_WAVE));
+      } else {
+        __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(0));
+      }
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+      if (x + 2 < nst) issue_buf(x + 2, (int)((x + 2) % kNBuf));
+    };
+    auto a_at = [&](int buf, int s) -> const intx4 & { return lds[buf][(wm * S + s) * 64 + lane]; };
+    auto b_at = [&](int buf, int t) -> const intx4 & { return lds[buf][C::A_CH * 64 + (wn * S + t) * 64 + lane]; };
+    asm volatile("" ::"s"(rowmax), "s"(colmax), "s"(D));
     intx4 af[S], bfr[S];
+    issue_buf(0, 0);
+    if (1 < nst) issue_buf(1, 1);
+    open_stage(0);
 #pragma unroll
-    for (int s = 0; s < S; ++s) af[s] = lds[buf][(wm * S + s) * 64 + lane];
-#pragma unroll
-    for (int t = 0; t < S; ++t) bfr[t] = lds[buf][C::A_CH * 64 + (wn * S + t) * 64 + lane];
+    for (int r = 0; r < S; ++r) {
+      bfr[S - 1 - r] = b_at(0, S - 1 - r);
+      af[r] = a_at(0, r);
+    }
     __builtin_amdgcn_sched_barrier(0);
+    auto run_stage = [&]<bool MORE>(int64_t st) {
+      const int nbuf = (int)((st + 1) % kNBuf);
 #pragma unroll
-    for (int r = 0; r < S; ++r)
+      for (int d = S - 1; d >= 0; --d) acc[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[0], bfr[d], acc[d], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (MORE) {
+        open_stage(st + 1);
+        bfr[S - 1] = b_at(nbuf, S - 1);
+        af[0] = a_at(nbuf, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
 #pragma unroll
-      for (int d = S - 1; d >= r; --d) acc[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bfr[d - r], acc[d], 0, 0, 0);
-    if ((st + 1) % kFoldStages == 0) fold_all();
+      for (int r = 1; r < S; ++r) {
+#pragma unroll
+        for (int d = S - 1; d >= r; --d) {
+          acc[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bfr[d - r], acc[d], 0, 0, 0);
+          if constexpr (MORE)
+            if (d == S - 1) {
+              __builtin_amdgcn_sched_barrier(0);
+              bfr[S - 1 - r] = b_at(nbuf, S - 1 - r);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if constexpr (MORE) {
+          af[r] = a_at(nbuf, r);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if ((st + 1) % kFoldStages == 0) fold_all();
+    };
+    for (int64_t st = 0; st + 1 < nst; ++st) run_stage.template operator()<true>(st);
+    run_stage.template operator()<false>(nst - 1);
+  } else {
+    issue_stage(0, 0);
+    if (1 < nst) issue_stage(1, 1);
+    for (int64_t st = 0; st < nst; ++st) {
+      const int buf = (int)(st % kNBuf);
+      // The copies of stage st + 1 may stay in flight.
+      if (st + 1 < nst) {
+        if (wave < C::EXTRA)
+          __builtin_amdgcn_s_waitcnt(0x0F70 | C::MAX_WAVE);
+        else
+          __builtin_amdgcn_s_waitcnt(0x0F70 | C::PER_WAVE);
+      } else {
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+      }
+      // Plain barrier (no fence): this stage is visible, and the buffer of
+      // stage st - 1 is free for stage st + 2.
+      __builtin_amdgcn_s_barrier();
+      if (st + 2 < nst) issue_stage(st + 2, (int)((st + 2) % kNBuf));
+      intx4 af[S], bfr[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) af[s] = lds[buf][(wm * S + s) * 64 + lane];
+#pragma unroll
+      for (int t = 0; t < S; ++t) bfr[t] = lds[buf][C::A_CH * 64 + (wn * S + t) * 64 + lane];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < S; ++r)
+#pragma unroll
+        for (int d = S - 1; d >= r; --d)
+          acc[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bfr[d - r], acc[d], 0, 0, 0);
+      if ((st + 1) % kFoldStages == 0) fold_all();
+    }
   }
   if (nst % kFoldStages != 0) fold_all();
 

@@ -147,6 +147,136 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_f8(
   }
 }
 
+// Pipelined FP8 kernel over one slab of stages [st_lo, st_hi), at most
+// kFoldStages of them (4096 k): the host launches it once per slab, and each
+// launch folds its level accumulators into D once, at the end. A stage's A and
+// B fragments all sit in registers (S of each); the barrier of stage st + 1
+// comes after round 0 of stage st, and each fragment register is refilled
+// with the next stage's right after its last MFMA (B fragment t: first MFMA
+// of round S - 1 - t; A fragment r: last MFMA of round r), so LDS reads run
+// under the matrix-core work. The copies are buffer loads into LDS, one
+// descriptor per operand tile with the chunk's offset in the scalar offset
+// (with global_load_lds in flight the compiler cannot order LDS reads and
+// waits for all of them at every use). One fold per launch keeps the level
+// accumulators in the accumulation registers; a fold inside this loop, with
+// both operand sets live, made the compiler spill.
+// Slab 0 writes D, later slabs add to it in the same order as the other
+// kernel's folds, and the last slab applies the exact power-of-two descale.
+template <int S, int WMW, int WNW>
+__global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_f8_slab(
+    const intx4 *__restrict__ Apk, const intx4 *__restrict__ Bpk, const uint64_t *__restrict__ rowmax,
+    const uint64_t *__restrict__ colmax, double *__restrict__ D, int64_t M, int64_t N, int64_t KB, int64_t tiles_m,
+    int64_t tiles_n, int64_t st_lo, int64_t st_hi) {
+  using C = Cfg<S, WMW, WNW>;
+  __shared__ intx4 lds[kNBuf][C::ST_CH * 128];
+
+  int64_t tm, tn;
+  grouped_tile(xcd_swizzle(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 4, tm, tn);
+  const int tid = threadIdx.x, lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  __builtin_assume(wave >= 0 && wave < C::kWaves);
+  const int wm = wave / WNW, wn = wave % WNW;
+
+  const intx4 *abase = uniform_ptr(Apk + tm * C::MBW * KB * S * 128);
+  const intx4 *bbase = uniform_ptr(Bpk + tn * C::NBW * KB * S * 128);
+  const int a_bytes = (int)(C::MBW * KB * S * 2048), b_bytes = (int)(C::NBW * KB * S * 2048);
+  // Copies of a stage: A copy q is half (q % 2) of A chunk q / 2, likewise
+  // for B; every wave issues the same number of each.
+  static_assert((2 * C::A_CH) % C::kWaves == 0 && (2 * C::B_CH) % C::kWaves == 0, "uneven copies");
+  auto issue = [&](int64_t st, int buf) {
+#pragma unroll
+    for (int qq = 0; qq < 2 * C::A_CH / C::kWaves; ++qq) {
+      const int q = wave + C::kWaves * qq, c = q / 2, half = q % 2;
+      copy16_to_lds(abase, a_bytes, &lds[buf][c * 128 + half * 64], lane * 16,
+                    (int)(((c / S) * KB * S + c % S + st * S) * 2048 + half * 1024));
+    }
+#pragma unroll
+    for (int qq = 0; qq < 2 * C::B_CH / C::kWaves; ++qq) {
+      const int q = wave + C::kWaves * qq, c = q / 2, half = q % 2;
+      copy16_to_lds(bbase, b_bytes, &lds[buf][(C::A_CH + c) * 128 + half * 64], lane * 16,
+                    (int)(((c / S) * KB * S + c % S + st * S) * 2048 + half * 1024));
+    }
+  };
+  // Stage x becomes readable: its copies are done and, after this wave's
+  // LDS reads have drained, every wave has left the buffer that now takes
+  // stage x + 1 (the stage before x, whose fragments are all in registers).
+  auto open_stage = [&](int64_t x) {
+    __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(0));
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    if (x + 1 < st_hi) issue(x + 1, (int)((x + 1) % kNBuf));
+  };
+  auto frag = [&](int buf, int c) {
+    const intx4 lo = lds[buf][c * 128 + lane], hi = lds[buf][c * 128 + 64 + lane];
+    return intx8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  };
+
+  floatx16 acc[S];
+  const floatx16 zero16 = {};
+#pragma unroll
+  for (int d = 0; d < S; ++d) acc[d] = zero16;
+  asm volatile("" ::"s"(rowmax), "s"(colmax), "s"(D));
+  intx8 af[S], bfr[S];
+  issue(st_lo, (int)(st_lo % kNBuf));
+  open_stage(st_lo);
+  {
+    const int buf = (int)(st_lo % kNBuf);
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      bfr[S - 1 - r] = frag(buf, C::A_CH + wn * S + S - 1 - r);
+      af[r] = frag(buf, wm * S + r);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // The last stage runs the same body: it opens stage st_hi, which has no
+  // copies (a barrier only), and refills the registers with LDS contents
+  // nothing uses.
+  for (int64_t st = st_lo; st < st_hi; ++st) {
+    const int nbuf = (int)((st + 1) % kNBuf);
+#pragma unroll
+    for (int d = S - 1; d >= 0; --d) acc[d] = mfma_f8(af[0], bfr[d], acc[d]);
+    __builtin_amdgcn_sched_barrier(0);
+    open_stage(st + 1);
+    bfr[S - 1] = frag(nbuf, C::A_CH + wn * S + S - 1);
+    af[0] = frag(nbuf, wm * S);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 1; r < S; ++r) {
+#pragma unroll
+      for (int d = S - 1; d >= r; --d) {
+        acc[d] = mfma_f8(af[r], bfr[d - r], acc[d]);
+        if (d == S - 1) {
+          __builtin_amdgcn_sched_barrier(0);
+          bfr[S - 1 - r] = frag(nbuf, C::A_CH + wn * S + S - 1 - r);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      af[r] = frag(nbuf, wm * S + r);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // Fold into D: D[i, j] (+)= sum_d 2^-5d level_d, then on the last slab
+  // D[i, j] = 2^(e_i + f_j - 2(beta-1)) * D[i, j].
+  const bool first = st_lo == 0, last = st_hi == KB;
+  const int64_t gn = tn * C::BN + wn * 32 + lane % 32;
+  const int64_t row_base = tm * C::BM + wm * 32;
+  const int fe = (last && gn < N) ? exponent_of_max(colmax[gn]) : 0;
+  const int e_lane = (last && row_base + lane % 32 < M) ? exponent_of_max(rowmax[row_base + lane % 32]) : 0;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int r = (v / 4) * 8 + (lane / 32) * 4 + (v % 4);
+    const int ee = __shfl(e_lane, r);
+    const int64_t gm = row_base + r;
+    if (gm < M && gn < N) {
+      double t = first ? 0.0 : D[gm * N + gn];
+#pragma unroll
+      for (int d = S - 1; d >= 0; --d) t = fma((double)acc[d][v], __builtin_ldexp(1.0, -kBeta * d), t);
+      D[gm * N + gn] = last ? ldexp(t, ee + fe - 2 * (kBeta - 1)) : t;
+    }
+  }
+}
+
 }  // namespace f8
 
 }  // namespace split
