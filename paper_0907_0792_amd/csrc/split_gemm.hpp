@@ -276,14 +276,11 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
     // after every barrier, when all waves would wait on them together.
     // B fragment t is last used by the first MFMA of round S - 1 - t, A
     // fragment r by the last MFMA of round r.
-    static_assert(WN == 2 && SKB == 1 && NBUF == 3, "pipelined form: 32 x 64 wave blocks, three 16-k stages");
+    static_assert(WN == 2 && SKB == 1 && NBUF >= 3 && NBUF <= 4, "pipelined form: 32 x 64 wave blocks, 16-k stages");
     auto a_at = [&](int buf, int s) -> const bf16x8 & { return lds[buf][(wm * S + s) * 64 + lane]; };
     auto b_at = [&](int buf, int j, int t) -> const bf16x8 & {
       return lds[buf][C::A_CH * 64 + ((wn * WN + j) * S + t) * 64 + lane];
     };
-    // Stage x becomes readable: its copies are done (the next stage's may
-    // stay in flight), every wave has left the fragments of stage x - 1, and
-    // that buffer is refilled with stage x + 2.
     // Copies by buffer loads into LDS: chunk stream q of this wave gets a
     // descriptor at its stage-0 chunk covering its nst chunks (the host keeps
     // that below 2^31 bytes); the stage offset goes in the scalar offset.
@@ -298,26 +295,32 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
         copy16_to_lds(cbase[q], stream_bytes, &lds[buf][c * 64], lane * 16, (int)st * (S * 64 * 16));
       }
     };
+    // Stage x becomes readable: its copies are done (the ones of the stages
+    // after it that are already issued may stay in flight), every wave has
+    // left the fragments of stage x - 1, and that buffer is refilled with
+    // stage x + NBUF - 1.
+    static_assert(C::EXTRA == 0, "pipelined form: every wave issues the same copies");
+    auto wait_vm = [&]<int N>() { __builtin_amdgcn_s_waitcnt(vmcnt_imm(N)); };
     auto open_stage = [&](int64_t x) {
-      if (x + 1 < nst) {
-        if (wave < C::EXTRA)
-          __builtin_amdgcn_s_waitcnt(vmcnt_imm(C::MAX_WAVE));
-        else
-          __builtin_amdgcn_s_waitcnt(vmcnt_imm(C::PER_WAVE));
-      } else {
-        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-      }
+      const int64_t later = nst - 1 - x;  // stages after x
+      if (later >= NBUF - 2)
+        wait_vm.template operator()<(NBUF - 2) * C::PER_WAVE>();
+      else if (NBUF > 3 && later == 1)
+        wait_vm.template operator()<C::PER_WAVE>();
+      else
+        wait_vm.template operator()<0>();
       __builtin_amdgcn_s_barrier();
       __builtin_amdgcn_sched_barrier(0);
-      if (x + 2 < nst) issue_buf(x + 2, (int)((x + 2) % NBUF));
+      if (x + NBUF - 1 < nst) issue_buf(x + NBUF - 1, (int)((x + NBUF - 1) % NBUF));
     };
     // The epilogue's kernel arguments are loaded here, before the loop: a
     // scalar load still in flight would make every LDS wait in the loop a
     // full drain (scalar loads complete out of order on the same counter).
     asm volatile("" ::"s"(rowmax), "s"(colmax), "s"(D));
     bf16x8 af[S], bfr[S];
-    issue_buf(0, 0);
-    if (1 < nst) issue_buf(1, 1);
+#pragma unroll
+    for (int i = 0; i < NBUF - 1; ++i)
+      if (i < nst) issue_buf(i, i);
     open_stage(0);
     // Same read order as the loop's refills, so the waits at the loop head
     // are the same from both sides.
