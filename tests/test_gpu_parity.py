@@ -1160,8 +1160,9 @@ def test_fp32_batch_exact_integers_32bit_index():
 
 # ---------------------------------------------------------------------------
 # Split products with K past 8192: the INT8 kernel folds its INT32 levels into
-# FP64 in the middle of the loop (every 8192 k), the BF16 kernel runs a
-# 64-k tail after its unrolled 256-k cycles.
+# FP64 in the middle of the loop (every 8192 k), the FP8 product runs as three
+# 4096-k slab launches (the last one partial) that accumulate in D, and the
+# BF16 kernel ends inside its 256-k fold cycle.
 
 @pytest.mark.parametrize("fmt,S,beta", [("bf16", 5, 9), ("int8", 7, 7), ("fp8", 10, 5)])
 def test_split_contraction_longer_than_8192(fmt, S, beta):
