@@ -14,7 +14,7 @@
 // The table maps (M, N, K) size buckets to a variant; moa_batch_autotune
 // fills it by timing both variants on synthetic problems of each bucket.
 // FP32 batches whose operands allow 32-bit byte offsets run the LDS-fed
-// tile (batch_tile_lds: buffer loads straight into an LDS ring); FP64 and
+// tile (batch_tile_lds16: buffer loads straight into an LDS ring); FP64 and
 // larger FP32 batches run the register-staged tile of gemm_tile.hpp.
 #include <stdio.h>
 #include <string.h>
@@ -102,34 +102,41 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchItem *__restrict__ 
 // of 16 are in flight per workgroup at no register cost; one barrier per
 // panel. Elements past M, N or K get an offset past the buffer's size, and
 // the buffer range check returns zero for them.
-// A panel (rows of 16 k, 64 bytes each): load (ib, rg) has lane l fetch
-// A[16 ib + 4 rg + l / 16][l % 16], four rows of 64 bytes (four cache
-// lines, as a row-major read), into an LDS block of 64 words padded to 68.
-// The v_mfma_f32_16x16x4_f32 fragment of k step ks wants
-// A[16 ib + i][4 ks + c] in lane i + 16 c; it sits in block (ib, i / 4) at
-// word (i % 4) 16 + 4 ks + c, and with the padding the 64 lanes' words fall
-// in 64 different banks.
-// B panel: load (jb, ks) has lane l fetch B[4 ks + l / 16][16 jb + l % 16],
-// which is exactly the fragment's lane order (four rows of 64 bytes).
 // Three panels: six workgroups per CU (LDS-bound), two panels in flight
-// each. On the 10,000-problem FP32 workload, same box: 0.2256 ms against
-// 0.2343 with four panels (four workgroups per CU) and 0.243-0.246 ms for the
-// register-staged tile; loading A fragment-ordered by 4-byte lanes (each
-// load touching 16 rows) instead measured 0.281-0.287 ms.
+// each. History on the 10,000-problem FP32 workload (same box per pair):
+// loading 4 bytes per lane (four 256-byte rows per load, A blocks padded
+// to 68 words) 0.2256 ms against 0.2343 with four panels and 0.243-0.246 ms
+// for the register-staged tile; A fragment-ordered by 4-byte lanes (each
+// load touching 16 rows) 0.281-0.287 ms; 16 bytes per lane (below)
+// 0.2147-0.2173 ms against 0.2237-0.2277 ms for 4 bytes per lane.
 constexpr int kLdsStages = 3;
-constexpr int kLdsBlock = 68;  // words per A load block (64 + 4 of padding)
+constexpr int kLdsStageWords = 2 * 4 * 256;  // A then B: four 16 x 16 blocks each
 
 // s_waitcnt immediate that waits until at most n vector-memory operations
 // are outstanding (n < 64) and leaves the other counters alone.
 constexpr int vmcnt_lds(int n) { return 0x0F70 | (n & 15) | ((n >> 4) << 14); }
 
+// The tile is fed by 16-byte buffer loads: one instruction moves a whole
+// 16 x 16 block (1 KiB). A block: lane l loads
+// A[16 ib + l % 16][k0 + 4 (l / 16) .. + 3], which lands in 16-byte slot l,
+// so word 64 ks + 4 i + c holds A[16 ib + i][k0 + 4 ks + c]: the fragment
+// read of lane i + 16 c touches 64 different banks. B block: lane l loads
+// B[k0 + l / 4][16 jb + 4 (l % 4) .. + 3], so word 16 k + j holds B[k0 + k][j]
+// and the fragment word 64 ks + 16 c + j is again conflict-free. A 4-element
+// run is loaded whole or not at all, so the last k panel (where runs may
+// cross K, or for B the end of the buffer) loads the same layout with four
+// 4-byte loads per block and masks each element: instruction t has lane l
+// fill word 64 t + l. B columns past N inside a run hold other data, which
+// reaches only D columns past N, which are not stored.
 template <int WB, int NS>
-__device__ __forceinline__ void batch_tile_lds(const BatchItem &w, float *lds) {
-  constexpr int NB = 2 * WB;                          // 16-wide blocks per tile side
-  constexpr int ASZ = 4 * 4 * kLdsBlock;              // A words per stage (sized for WB = 2)
-  constexpr int STAGE = ASZ + 4 * 4 * 64;             // then B
-  constexpr uint32_t kOut = 0x80000000u;              // an offset past every buffer
+__device__ __forceinline__ void batch_tile_lds16(const BatchItem &w, float *lds) {
+  constexpr int NB = 2 * WB;                // 16-wide blocks per tile side
+  constexpr int ASZ = 4 * 256;              // A words per stage (sized for WB = 2)
+  constexpr int STAGE = kLdsStageWords;     // then B
+  constexpr int BPW = NB / 2;               // blocks per wave per panel
+  constexpr uint32_t kOut = 0x80000000u;    // an offset past every buffer
   using MF = Mfma16<float>;
+  typedef __attribute__((address_space(3))) void *lds_ptr;
   const int lane = threadIdx.x % kWave, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int wm = wave / 2, wn = wave % 2;
   const int M = w.M, K = w.K, N = w.N, m0 = w.m0, n0 = w.n0;
@@ -137,32 +144,49 @@ __device__ __forceinline__ void batch_tile_lds(const BatchItem &w, float *lds) {
       __builtin_amdgcn_make_buffer_rsrc((void *)w.A, (short)0, (int)((uint32_t)M * (uint32_t)K * 4u), 0x00020000);
   const __amdgpu_buffer_rsrc_t rb =
       __builtin_amdgcn_make_buffer_rsrc((void *)w.B, (short)0, (int)((uint32_t)K * (uint32_t)N * 4u), 0x00020000);
-  // This wave's loads: A blocks q = wave NB + p = (ib, rg) = (q / 4, q % 4)
-  // and B blocks q = (jb, ks) = (q / 4, q % 4), p < NB.
-  uint32_t abase[NB], bbase[NB];
-  int bkk[NB];
-  bool arow[NB], bcol[NB];
-  const int acol = lane % 16;
+  const int nk = (K + 15) / 16;
+  // One block's loads for panel kt into stage buffer st (A or B fixed at
+  // compile time, so each load names its descriptor directly).
+  auto issue_block = [&]<bool ISA>(float *st, int blk, int kt) {
+    const int k0 = 16 * kt;
+    float *dst = st + (ISA ? 0 : ASZ) + blk * 256;
+    if (kt + 1 < nk) {
+      uint32_t off;
+      if constexpr (ISA) {
+        const int row = m0 + 16 * blk + lane % 16, k = k0 + 4 * (lane / 16);
+        off = row < M ? ((uint32_t)row * (uint32_t)K + (uint32_t)k) * 4u : kOut;
+      } else {
+        const int k = k0 + lane / 4, col = n0 + 16 * blk + 4 * (lane % 4);
+        off = col < N ? ((uint32_t)k * (uint32_t)N + (uint32_t)col) * 4u : kOut;
+      }
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ISA ? ra : rb, (lds_ptr)dst, 16, off, 0, 0, 0);
+    } else {
 #pragma unroll
-  for (int p = 0; p < NB; ++p) {
-    const int q = wave * NB + p;
-    const int row = m0 + 16 * (q / 4) + 4 * (q % 4) + lane / 16;
-    const int col = n0 + 16 * (q / 4) + lane % 16;
-    bkk[p] = 4 * (q % 4) + lane / 16;
-    arow[p] = row < M;
-    bcol[p] = col < N;
-    abase[p] = (uint32_t)row * (uint32_t)K + (uint32_t)acol;
-    bbase[p] = (uint32_t)bkk[p] * (uint32_t)N + (uint32_t)col;
-  }
-  auto issue = [&](int buf, int k0) {
-    typedef __attribute__((address_space(3))) void *lds_ptr;
-#pragma unroll
-    for (int p = 0; p < NB; ++p) {
-      const int q = wave * NB + p;
-      const uint32_t oa = (arow[p] && k0 + acol < K) ? (abase[p] + (uint32_t)k0) * 4u : kOut;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)(lds + buf * STAGE + q * kLdsBlock), 4, oa, 0, 0, 0);
-      const uint32_t ob = (bcol[p] && k0 + bkk[p] < K) ? (bbase[p] + (uint32_t)k0 * (uint32_t)N) * 4u : kOut;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr)(lds + buf * STAGE + ASZ + q * 64), 4, ob, 0, 0, 0);
+      for (int t = 0; t < 4; ++t) {
+        uint32_t off;
+        if constexpr (ISA) {
+          const int row = m0 + 16 * blk + lane / 4, k = k0 + 4 * t + lane % 4;
+          off = (row < M && k < K) ? ((uint32_t)row * (uint32_t)K + (uint32_t)k) * 4u : kOut;
+        } else {
+          const int k = k0 + 4 * t + lane / 16, col = n0 + 16 * blk + lane % 16;
+          off = (k < K && col < N) ? ((uint32_t)k * (uint32_t)N + (uint32_t)col) * 4u : kOut;
+        }
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ISA ? ra : rb, (lds_ptr)(dst + 64 * t), 4, off, 0, 0, 0);
+      }
+    }
+  };
+  // Blocks of this wave: with 4 blocks a side, A block `wave` and B block
+  // `wave`; with 2, waves 0-1 take the A blocks and waves 2-3 the B blocks.
+  auto issue = [&](int buf, int kt) {
+    float *st = lds + buf * STAGE;
+    if constexpr (NB == 4) {
+      issue_block.template operator()<true>(st, wave, kt);
+      issue_block.template operator()<false>(st, wave, kt);
+    } else {
+      if (wave < 2)
+        issue_block.template operator()<true>(st, wave, kt);
+      else
+        issue_block.template operator()<false>(st, wave - 2, kt);
     }
   };
   // Blocks of this wave inside the problem: no MFMA for the others.
@@ -174,32 +198,31 @@ __device__ __forceinline__ void batch_tile_lds(const BatchItem &w, float *lds) {
   for (int i = 0; i < WB; ++i)
 #pragma unroll
     for (int j = 0; j < WB; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // Fragment word offsets of this lane inside a stage.
-  const int ai = lane % 16, ac = lane / 16;
-  const int afrag = (ai / 4) * kLdsBlock + (ai % 4) * 16 + ac;
+  const int fi = lane % 16, fc = lane / 16;
 
-  const int nk = (K + 15) / 16;
 #pragma unroll
   for (int st = 0; st < NS - 1; ++st)
-    if (st < nk) issue(st, 16 * st);
+    if (st < nk) issue(st, st);
   for (int kt = 0; kt < nk; ++kt) {
     // This wave's loads of panel kt are done once at most the later panels'
-    // loads (2 NB each) are outstanding; the barrier then makes every wave's
-    // part visible and frees the buffer of panel kt - 1.
+    // loads are outstanding (counted at BPW each; the last panel issues
+    // more, so near the end the wait is stricter than needed); the barrier
+    // then makes every wave's part visible and frees the buffer of panel
+    // kt - 1.
     if (kt + NS - 2 < nk)
-      __builtin_amdgcn_s_waitcnt(vmcnt_lds(2 * NB * (NS - 2)));
+      __builtin_amdgcn_s_waitcnt(vmcnt_lds(BPW * (NS - 2)));
     else
       __builtin_amdgcn_s_waitcnt(vmcnt_lds(0));
     __builtin_amdgcn_s_barrier();
-    if (kt + NS - 1 < nk) issue((kt + NS - 1) % NS, 16 * (kt + NS - 1));
+    if (kt + NS - 1 < nk) issue((kt + NS - 1) % NS, kt + NS - 1);
     const float *stage = lds + (kt % NS) * STAGE;
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       float a[WB], b[WB];
 #pragma unroll
-      for (int i = 0; i < WB; ++i) a[i] = stage[(wm * WB + i) * 4 * kLdsBlock + afrag + 4 * ks];
+      for (int i = 0; i < WB; ++i) a[i] = stage[(wm * WB + i) * 256 + 64 * ks + 4 * fi + fc];
 #pragma unroll
-      for (int j = 0; j < WB; ++j) b[j] = stage[ASZ + ((wn * WB + j) * 4 + ks) * 64 + lane];
+      for (int j = 0; j < WB; ++j) b[j] = stage[ASZ + (wn * WB + j) * 256 + 64 * ks + 16 * fc + fi];
 #pragma unroll
       for (int i = 0; i < WB; ++i)
 #pragma unroll
@@ -224,7 +247,7 @@ __device__ __forceinline__ void batch_tile_lds(const BatchItem &w, float *lds) {
 template <int NS>
 __global__ __launch_bounds__(256, 2) void k_batch_lds(const BatchItem *__restrict__ items,
                                                        const int64_t *__restrict__ first) {
-  __shared__ __attribute__((aligned(16))) float lds[NS * (4 * 4 * kLdsBlock + 4 * 4 * 64)];
+  __shared__ __attribute__((aligned(16))) float lds[NS * kLdsStageWords];
   int64_t it = first[blockIdx.x];
   const int64_t end = first[blockIdx.x + 1];
   if (it >= end) return;
@@ -232,9 +255,9 @@ __global__ __launch_bounds__(256, 2) void k_batch_lds(const BatchItem *__restric
   for (; it < end; ++it) {
     const BatchItem wn = items[it + 1 < end ? it + 1 : it];  // uniform: a scalar load
     if (w.tile == 0)
-      batch_tile_lds<1, NS>(w, lds);
+      batch_tile_lds16<1, NS>(w, lds);
     else
-      batch_tile_lds<2, NS>(w, lds);
+      batch_tile_lds16<2, NS>(w, lds);
     w = wn;
   }
 }
