@@ -108,7 +108,8 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchItem *__restrict__ 
 // to 68 words) 0.2256 ms against 0.2343 with four panels and 0.243-0.246 ms
 // for the register-staged tile; A fragment-ordered by 4-byte lanes (each
 // load touching 16 rows) 0.281-0.287 ms; 16 bytes per lane (below)
-// 0.2147-0.2173 ms against 0.2237-0.2277 ms for 4 bytes per lane.
+// 0.2147-0.2173 ms against 0.2237-0.2277 ms for 4 bytes per lane, and
+// 0.2385-0.2415 ms with four panels (five workgroups per CU).
 constexpr int kLdsStages = 3;
 constexpr int kLdsStageWords = 2 * 4 * 256;  // A then B: four 16 x 16 blocks each
 
