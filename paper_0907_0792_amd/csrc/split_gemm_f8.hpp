@@ -183,28 +183,43 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_f8_slab(
   // Copies of a stage: A copy q is half (q % 2) of A chunk q / 2, likewise
   // for B; every wave issues the same number of each.
   static_assert((2 * C::A_CH) % C::kWaves == 0 && (2 * C::B_CH) % C::kWaves == 0, "uneven copies");
-  auto issue = [&](int64_t st, int buf) {
-#pragma unroll
-    for (int qq = 0; qq < 2 * C::A_CH / C::kWaves; ++qq) {
-      const int q = wave + C::kWaves * qq, c = q / 2, half = q % 2;
-      copy16_to_lds(abase, a_bytes, &lds[buf][c * 128 + half * 64], lane * 16,
-                    (int)(((c / S) * KB * S + c % S + st * S) * 2048 + half * 1024));
-    }
-#pragma unroll
-    for (int qq = 0; qq < 2 * C::B_CH / C::kWaves; ++qq) {
-      const int q = wave + C::kWaves * qq, c = q / 2, half = q % 2;
-      copy16_to_lds(bbase, b_bytes, &lds[buf][(C::A_CH + c) * 128 + half * 64], lane * 16,
-                    (int)(((c / S) * KB * S + c % S + st * S) * 2048 + half * 1024));
-    }
+  // voff: the lanes' offset, or one past every buffer (the loads then return
+  // zeros and touch no memory), which lets a copy be skipped without a branch.
+  constexpr int NA = 2 * C::A_CH / C::kWaves, NB = 2 * C::B_CH / C::kWaves;  // copies per wave
+  auto copy_a = [&](int64_t st, int buf, int voff, int qq) {
+    const int q = wave + C::kWaves * qq, c = q / 2, half = q % 2;
+    copy16_to_lds(abase, a_bytes, &lds[buf][c * 128 + half * 64], voff,
+                  (int)(((c / S) * KB * S + c % S + st * S) * 2048 + half * 1024));
   };
+  auto copy_b = [&](int64_t st, int buf, int voff, int qq) {
+    const int q = wave + C::kWaves * qq, c = q / 2, half = q % 2;
+    copy16_to_lds(bbase, b_bytes, &lds[buf][(C::A_CH + c) * 128 + half * 64], voff,
+                  (int)(((c / S) * KB * S + c % S + st * S) * 2048 + half * 1024));
+  };
+  auto issue_a = [&](int64_t st, int buf, int voff) {
+#pragma unroll
+    for (int qq = 0; qq < NA; ++qq) copy_a(st, buf, voff, qq);
+  };
+  auto issue_b = [&](int64_t st, int buf, int voff) {
+#pragma unroll
+    for (int qq = 0; qq < NB; ++qq) copy_b(st, buf, voff, qq);
+  };
+  constexpr int kNoCopy = (int)0x80000000u;
   // Stage x becomes readable: its copies are done and, after this wave's
-  // LDS reads have drained, every wave has left the buffer that now takes
-  // stage x + 1 (the stage before x, whose fragments are all in registers).
+  // LDS reads have drained, every wave has left the buffer that takes stage
+  // x + 1 next (the stage before x, whose fragments are all in registers).
+  // With one wave per SIMD nothing covers a burst of copies, so from three
+  // slices on the copies of stage x + 1 are spread over the MFMAs of rounds
+  // 1 (A) and 2 (B) of stage x - 1, one or two after each; with fewer, here.
   auto open_stage = [&](int64_t x) {
     __builtin_amdgcn_s_waitcnt(vmcnt_lgkm0_imm(0));
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
-    if (x + 1 < st_hi) issue(x + 1, (int)((x + 1) % kNBuf));
+    if constexpr (S < 3)
+      if (x + 1 < st_hi) {
+        issue_a(x + 1, (int)((x + 1) % kNBuf), lane * 16);
+        issue_b(x + 1, (int)((x + 1) % kNBuf), lane * 16);
+      }
   };
   auto frag = [&](int buf, int c) {
     const intx4 lo = lds[buf][c * 128 + lane], hi = lds[buf][c * 128 + 64 + lane];
@@ -217,8 +232,14 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_f8_slab(
   for (int d = 0; d < S; ++d) acc[d] = zero16;
   asm volatile("" ::"s"(rowmax), "s"(colmax), "s"(D));
   intx8 af[S], bfr[S];
-  issue(st_lo, (int)(st_lo % kNBuf));
+  issue_a(st_lo, (int)(st_lo % kNBuf), lane * 16);
+  issue_b(st_lo, (int)(st_lo % kNBuf), lane * 16);
   open_stage(st_lo);
+  if constexpr (S >= 3)
+    if (st_lo + 1 < st_hi) {
+      issue_a(st_lo + 1, (int)((st_lo + 1) % kNBuf), lane * 16);
+      issue_b(st_lo + 1, (int)((st_lo + 1) % kNBuf), lane * 16);
+    }
   {
     const int buf = (int)(st_lo % kNBuf);
 #pragma unroll
@@ -245,11 +266,27 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_f8_slab(
 #pragma unroll
       for (int d = S - 1; d >= r; --d) {
         acc[d] = mfma_f8(af[r], bfr[d - r], acc[d]);
-        if (d == S - 1) {
-          __builtin_amdgcn_sched_barrier(0);
-          bfr[S - 1 - r] = frag(nbuf, C::A_CH + wn * S + S - 1 - r);
-          __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (d == S - 1) bfr[S - 1 - r] = frag(nbuf, C::A_CH + wn * S + S - 1 - r);
+        // Stage st + 2 goes to the buffer of stage st, whose fragments every
+        // wave has read (open_stage(st + 1) above). Copy qq follows MFMA
+        // qq * len / n of its round. Past the slab's end the copies are
+        // issued as no-ops, so no branch here lets the compiler move them.
+        if constexpr (S >= 3) {
+          if (r == 1 || r == 2) {
+            const int voff = st + 2 < st_hi ? lane * 16 : kNoCopy;
+            const int len = S - r, i = S - 1 - d;
+#pragma unroll
+            for (int qq = 0; qq < (r == 1 ? NA : NB); ++qq)
+              if (qq * len / (r == 1 ? NA : NB) == i) {
+                if (r == 1)
+                  copy_a(st + 2, (int)(st % kNBuf), voff, qq);
+                else
+                  copy_b(st + 2, (int)(st % kNBuf), voff, qq);
+              }
+          }
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
       af[r] = frag(nbuf, wm * S + r);
       __builtin_amdgcn_sched_barrier(0);
