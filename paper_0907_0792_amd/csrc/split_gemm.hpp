@@ -295,6 +295,13 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
         copy16_to_lds(cbase[q], stream_bytes, &lds[buf][c * 64], lane * 16, (int)st * (S * 64 * 16));
       }
     };
+    // Copy q of stage st; voff = kNoCopy (an offset past the stream) makes it
+    // a no-op that reads no memory, so a copy past the last stage needs no
+    // branch.
+    constexpr int kNoCopy = (int)0x80000000u;
+    auto copy_one = [&](int64_t st, int buf, int voff, int q) {
+      copy16_to_lds(cbase[q], stream_bytes, &lds[buf][(wave + C::kWaves * q) * 64], voff, (int)st * (S * 64 * 16));
+    };
     // Stage x becomes readable: its copies are done (the ones of the stages
     // after it that are already issued may stay in flight), every wave has
     // left the fragments of stage x - 1, and that buffer is refilled with
@@ -311,7 +318,10 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
         wait_vm.template operator()<0>();
       __builtin_amdgcn_s_barrier();
       __builtin_amdgcn_sched_barrier(0);
-      if (x + NBUF - 1 < nst) issue_buf(x + NBUF - 1, (int)((x + NBUF - 1) % NBUF));
+      // With two slices or more the copies of stage x + NBUF - 1 are spread
+      // over the MFMAs after this barrier (run_stage); with one, here.
+      if constexpr (S == 1)
+        if (x + NBUF - 1 < nst) issue_buf(x + NBUF - 1, (int)((x + NBUF - 1) % NBUF));
     };
     // The epilogue's kernel arguments are loaded here, before the loop: a
     // scalar load still in flight would make every LDS wait in the loop a
@@ -322,6 +332,14 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
     for (int i = 0; i < NBUF - 1; ++i)
       if (i < nst) issue_buf(i, i);
     open_stage(0);
+    // Stage NBUF - 1: with two slices or more open_stage leaves its copies
+    // to the stage body, which issues those of stage st + NBUF; the first
+    // such stage is issued here.
+    if constexpr (S >= 2)
+      if (NBUF - 1 < nst) {
+#pragma unroll
+        for (int q = 0; q < C::PER_WAVE; ++q) copy_one(NBUF - 1, NBUF - 1, lane * 16, q);
+      }
     // Same read order as the loop's refills, so the waits at the loop head
     // are the same from both sides.
 #pragma unroll
@@ -358,18 +376,25 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
         __builtin_amdgcn_sched_barrier(0);
       }
       // Rounds 1.. of column block 1; fragments are replaced by the next
-      // stage's as they retire.
+      // stage's as they retire, and the copies of stage st + NBUF (into the
+      // buffer of stage st, which every wave has left) go one after every
+      // few MFMAs: copy q follows MFMA q * T / PER_WAVE of these T.
+      constexpr int T = S * (S - 1) / 2;
+      const int voff = st + NBUF < nst ? lane * 16 : kNoCopy;
 #pragma unroll
       for (int r = 1; r < S; ++r) {
 #pragma unroll
         for (int d = S - 1; d >= r; --d) {
           acc[acc_of<MG>(d)][1] = mfma_bf16(af[r], bfr[d - r], acc[acc_of<MG>(d)][1]);
-          if constexpr (MORE)
-            if (d == S - 1) {
-              __builtin_amdgcn_sched_barrier(0);
-              bfr[S - 1 - r] = b_at(nbuf, 0, S - 1 - r);
-              __builtin_amdgcn_sched_barrier(0);
-            }
+          if constexpr (MORE) {
+            __builtin_amdgcn_sched_barrier(0);
+            if (d == S - 1) bfr[S - 1 - r] = b_at(nbuf, 0, S - 1 - r);
+            const int t = (r - 1) * S - (r - 1) * r / 2 + (S - 1 - d);
+#pragma unroll
+            for (int q = 0; q < C::PER_WAVE; ++q)
+              if (q * T / C::PER_WAVE == t) copy_one(st + NBUF, buf, voff, q);
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
         if constexpr (MORE) {
           af[r] = a_at(nbuf, r);
@@ -523,6 +548,13 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_i8(
         copy16_to_lds(qbase[q], stream_bytes, &lds[buf][c * 64], lane * 16, (int)st * (S * 64 * 16));
       }
     };
+    // Copy q of stage st; voff = kNoCopy (an offset past the stream) makes it
+    // a no-op that reads no memory, so a copy past the last stage needs no
+    // branch.
+    constexpr int kNoCopy = (int)0x80000000u;
+    auto copy_one = [&](int64_t st, int buf, int voff, int q) {
+      copy16_to_lds(qbase[q], stream_bytes, &lds[buf][(wave + C::kWaves * q) * 64], voff, (int)st * (S * 64 * 16));
+    };
     // Stage x becomes readable: its copies are done (the next stage's may
     // stay in flight) and, after this wave's LDS reads have drained, every
     // wave has left the buffer that now takes stage x + 2.
@@ -537,7 +569,17 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_i8(
       }
       __builtin_amdgcn_s_barrier();
       __builtin_amdgcn_sched_barrier(0);
-      if (x + 2 < nst) issue_buf(x + 2, (int)((x + 2) % kNBuf));
+      // With two slices or more, every wave's first PER_WAVE copies of stage
+      // x + 2 are spread over the MFMAs after this barrier (run_stage) and
+      // only the extra copy of the first EXTRA waves goes here; with one
+      // slice, all of them.
+      if (x + 2 < nst) {
+        if constexpr (S == 1) {
+          issue_buf(x + 2, (int)((x + 2) % kNBuf));
+        } else if constexpr (C::EXTRA > 0) {
+          if (wave < C::EXTRA) copy_one(x + 2, (int)((x + 2) % kNBuf), lane * 16, C::PER_WAVE);
+        }
+      }
     };
     auto a_at = [&](int buf, int s) -> const intx4 & { return lds[buf][(wm * S + s) * 64 + lane]; };
     auto b_at = [&](int buf, int t) -> const intx4 & { return lds[buf][C::A_CH * 64 + (wn * S + t) * 64 + lane]; };
@@ -546,6 +588,14 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_i8(
     issue_buf(0, 0);
     if (1 < nst) issue_buf(1, 1);
     open_stage(0);
+    // Stage 2: with two slices or more open_stage issues only its extra
+    // copy and leaves the others to the stage body, which issues those of
+    // stage st + 3; the first such stage is issued here.
+    if constexpr (S >= 2)
+      if (2 < nst) {
+#pragma unroll
+        for (int q = 0; q < C::PER_WAVE; ++q) copy_one(2, 2, lane * 16, q);
+      }
 #pragma unroll
     for (int r = 0; r < S; ++r) {
       bfr[S - 1 - r] = b_at(0, S - 1 - r);
@@ -563,17 +613,24 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_i8(
         af[0] = a_at(nbuf, 0);
         __builtin_amdgcn_sched_barrier(0);
       }
+      // Copies of stage st + 3 (into the buffer of stage st, which every
+      // wave has left): copy q follows MFMA q * T / PER_WAVE of rounds 1...
+      constexpr int T = S * (S - 1) / 2;
+      const int voff = st + 3 < nst ? lane * 16 : kNoCopy;
 #pragma unroll
       for (int r = 1; r < S; ++r) {
 #pragma unroll
         for (int d = S - 1; d >= r; --d) {
           acc[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bfr[d - r], acc[d], 0, 0, 0);
-          if constexpr (MORE)
-            if (d == S - 1) {
-              __builtin_amdgcn_sched_barrier(0);
-              bfr[S - 1 - r] = b_at(nbuf, S - 1 - r);
-              __builtin_amdgcn_sched_barrier(0);
-            }
+          if constexpr (MORE) {
+            __builtin_amdgcn_sched_barrier(0);
+            if (d == S - 1) bfr[S - 1 - r] = b_at(nbuf, S - 1 - r);
+            const int t = (r - 1) * S - (r - 1) * r / 2 + (S - 1 - d);
+#pragma unroll
+            for (int q = 0; q < C::PER_WAVE; ++q)
+              if (q * T / (C::PER_WAVE > 0 ? C::PER_WAVE : 1) == t) copy_one(st + 3, (int)(st % kNBuf), voff, q);
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
         if constexpr (MORE) {
           af[r] = a_at(nbuf, r);
