@@ -405,6 +405,9 @@ __global__ __launch_bounds__(64 * WMW * WNW, MINB) void k_split_gemm(
     };
     for (int64_t st = 0; st + 1 < nst; ++st) run_stage.template operator()<true>(st);
     run_stage.template operator()<false>(nst - 1);
+    // The last stages issued no-op copies after their final wait: drain them
+    // so that no copy into LDS is outstanding when the workgroup ends.
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
   } else {
     for (int i = 0; i < NBUF - 1; ++i)
       if (i < nst) issue_stage(i, i);
@@ -641,6 +644,9 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_i8(
     };
     for (int64_t st = 0; st + 1 < nst; ++st) run_stage.template operator()<true>(st);
     run_stage.template operator()<false>(nst - 1);
+    // The last stages issued no-op copies after their final wait: drain them
+    // so that no copy into LDS is outstanding when the workgroup ends.
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
   } else {
     issue_stage(0, 0);
     if (1 < nst) issue_stage(1, 1);

@@ -293,6 +293,10 @@ __global__ __launch_bounds__(64 * WMW * WNW, 1) void k_split_gemm_f8_slab(
     }
   }
 
+  // The last stage issued no-op copies after its final wait: drain them so
+  // that no copy into LDS is outstanding when the workgroup ends.
+  __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+
   // Fold into D: D[i, j] (+)= sum_d 2^-5d level_d, then on the last slab
   // D[i, j] = 2^(e_i + f_j - 2(beta-1)) * D[i, j].
   const bool first = st_lo == 0, last = st_hi == KB;
