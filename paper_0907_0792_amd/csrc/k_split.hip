@@ -314,7 +314,10 @@ static void launch_scans(const SplitPlan &p, const double *A, const double *B, u
                          hipStream_t s) {
   hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)((p.Mp + 3) / 4)), dim3(256), 0, s, A, p.M, p.K, rowmax, p.Mp);
   hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((p.Np + 255) / 256)), dim3(256), 0, s, colmax, p.Np);
-  const int64_t band = 128;
+  // Bands of 128 rows, or wider where K would need more than 65535 of them
+  // (the grid's y extent).
+  int64_t band = 128;
+  while ((p.K + band - 1) / band > 65535) band *= 2;
   dim3 gcols((unsigned)((p.N + 255) / 256), (unsigned)((p.K + band - 1) / band));
   if (p.N > 0 && p.K > 0) hipLaunchKernelGGL(k_scan_cols, gcols, dim3(256), 0, s, B, p.K, p.N, band, colmax);
 }

@@ -1179,6 +1179,26 @@ def test_split_contraction_longer_than_8192(fmt, S, beta):
 
 
 # ---------------------------------------------------------------------------
+# Contractions long enough that a slice stream reaches 2^31 bytes: the
+# pipelined kernels' buffer descriptors cannot reach that far, so these run the
+# plain-loop kernels (BF16, INT8) and the single-launch FP8 kernel. The INT8
+# case also needs more than 65535 row bands in the column scan. A
+# componentwise bound (error over sum |a_k b_k|) allows the FP64 folds of
+# ~10^5 partial sums; a wrong index or a missed stage is off by far more.
+
+@pytest.mark.parametrize("fmt,S,K", [("bf16", 5, 6_800_000), ("int8", 7, 9_700_000), ("fp8", 10, 3_400_000)])
+def test_split_contraction_past_the_descriptor_reach(fmt, S, K):
+    rng = np.random.default_rng(191)
+    a = mi.scaled_f64(rng, (2, K))
+    b = mi.scaled_f64(rng, (K, 3))
+    say("split", fmt, "2 x %d . %d x 3" % (K, K))
+    d = host(G.inner_split(gpu(a), gpu(b), fmt, S))
+    ref = oracle.inner_dot2(a, b)
+    err = oracle.componentwise_error(d, ref, oracle.abs_product(a, b))
+    assert err <= 1e-11, err
+
+
+# ---------------------------------------------------------------------------
 # Differentiation through torch.autograd: MoaInner.apply forward, the
 # hand-written backward through torch.autograd.grad, against FP64 central
 # differences (L = <G, D> is linear in each element, so they are exact up to
